@@ -1,0 +1,184 @@
+/*
+ * tenom: TENO-M per-face high-order reconstruction on AMD Instinct MI355X
+ * (gfx950), after Li, Fu & Adams, "A low-dissipation shock-capturing
+ * framework with flexible nonlinear dissipation control" (arXiv 2010.13289).
+ *
+ * C ABI of libtenom.so.  Plain pointers and sizes only.
+ *
+ * Data layout (all calls):
+ *   - Every array pointer is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *     tensor's storage), FP64, C-contiguous, structure of arrays
+ *     [field][z][y][x] with x fastest.  Grids carry no ghost cells: the
+ *     boundary rule of each axis (periodic wrap or transmissive clamp,
+ *     i.e. zero-gradient ghosts) is applied inside the kernels.
+ *   - Fields: scalar system 1 field (u); Euler ndim+2 fields
+ *     (rho, rho*u, [rho*v], [rho*w], E), ideal gas with ratio `gamma`.
+ *   - Points are cell-centre point values of a finite-difference scheme
+ *     (Sec. 2): du_i/dt = -(F_{i+1/2} - F_{i-1/2})/dx along each axis.
+ *
+ * Ownership: the caller allocates and frees everything.  The library never
+ * allocates device memory on the compute path; only tenom_max_wave_speed
+ * and tenom_check_finite keep one small (16-byte) device buffer per device,
+ * allocated on first use and held until the process ends.  All compute
+ * calls enqueue asynchronously on `stream` (a hipStream_t passed as void*;
+ * NULL = the default stream) and do not synchronise, except where stated.
+ * Calls on different streams are independent; concurrent calls that write
+ * the same buffers race.
+ *
+ * Errors: every int-returning call returns TENOM_OK (0) or a negative code;
+ * no call aborts or throws across the ABI.  tenom_last_error() gives a
+ * message for the last failure on the calling thread.
+ */
+#ifndef TENOM_H
+#define TENOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ----------------------------------------------------- */
+#define TENOM_OK 0
+#define TENOM_EINVAL (-1)      /* null pointer, ndim not in {1,2,3}, an used
+                                  axis with fewer than K cells, axis >= ndim,
+                                  C_T < 0 or NaN, gamma <= 1 (Euler), dt <= 0
+                                  or non-finite, dx <= 0                   */
+#define TENOM_EUNSUPPORTED (-2) /* unknown scheme, limiter or system ID     */
+#define TENOM_EWORKSPACE (-3)  /* workspace smaller than
+                                  tenom_workspace_bytes()                   */
+#define TENOM_EHIP (-4)        /* HIP launch or runtime error              */
+#define TENOM_ENONFINITE (-5)  /* tenom_check_finite found NaN or Inf      */
+
+/* ---- identifiers -------------------------------------------------------- */
+/* Boundary rule per axis. */
+#define TENOM_BC_PERIODIC 0
+#define TENOM_BC_TRANSMISSIVE 1 /* zero-gradient: cell indices clamped    */
+
+/* Conservation law. */
+#define TENOM_SYS_SCALAR 0 /* u_t + a . grad u = 0, a = grid.adv            */
+#define TENOM_SYS_EULER 1  /* compressible Euler, ideal gas                 */
+
+/* Scheme: number of points K of the full stencil (Sec. 2.1, Table 1).
+ * K = 6: candidates S0..S3 on i-2..i+3; K = 8: S0..S5 on i-3..i+4.  The
+ * optimal weights d_k are the maximum-order ones (Sec. 3.3), so with every
+ * candidate smooth the scheme is the K-point linear scheme. */
+#define TENOM_SCHEME_6 6
+#define TENOM_SCHEME_8 8
+
+/* Filter applied to the candidates the cutoff marks nonsmooth (Sec. 3.2,
+ * Eq. mp_flux).  MP: Suresh-Huynh bounds with alpha = 1.25 and the given
+ * curvature measure and beta (Eqs. upper_limiter .. value_monotonicity_
+ * preserving), computed once per face and applied to each nonsmooth
+ * candidate.  TVD-type: one limited flux on the fixed stencil centred at i
+ * replaces every nonsmooth candidate (Sec. 3.2.3). */
+#define TENOM_LIM_MP 1         /* MP, d^M4, beta = 4 (the paper's default) */
+#define TENOM_LIM_TVD_MINMOD 2 /* f_i + minmod(f_i - f_{i-1}, f_{i+1} - f_i)/2 */
+#define TENOM_LIM_TVD5 3       /* Kim & Kim fifth-order TVD, alpha = 2      */
+
+/* ---- grid descriptor ---------------------------------------------------- */
+typedef struct tenom_grid {
+    int32_t ndim;   /* 1, 2 or 3                                            */
+    int32_t n[3];   /* cells along x, y, z (entries >= ndim are ignored)     */
+    double dx[3];   /* cell size along x, y, z (> 0 for used axes)           */
+    int32_t bc[3];  /* TENOM_BC_* per axis                                   */
+    int32_t system; /* TENOM_SYS_*                                           */
+    double adv[3];  /* advection velocity (scalar system only)               */
+} tenom_grid;
+
+/* Number of fields of the grid's system (1, or ndim + 2), 0 if invalid. */
+int tenom_num_fields(const tenom_grid* grid);
+
+/* ---- compute calls ------------------------------------------------------ */
+
+/*
+ * Numerical fluxes at every face of one axis (Sec. 2-3 and 4).
+ *
+ * For each face i+1/2 the K cells i-K/2+1 .. i+K/2 along `axis` are read;
+ * for the Euler system they are projected on the left eigenvectors of the
+ * flux Jacobian at the Roe average of cells i and i+1 and split by the
+ * Rusanov (local Lax-Friedrichs) rule f+- = (F +- alpha U)/2, alpha = the
+ * largest |u_n| + c over the K cells (scalar system: f = a u, alpha = |a|).
+ * Each split component is reconstructed by TENO-M: candidate fluxes
+ * (Table 1), smoothness indicators and tau_K (Eqs. measureTENO, taukTENO),
+ * the sharp cutoff chi_k < C_T -> nonsmooth (Eqs. normalize, cut-off), the
+ * limiter on the nonsmooth candidates (Eq. mp_flux) and assembly with the
+ * optimal weights, no renormalisation (Eq. reconstuction).  The f- side is
+ * the mirror image about the face.  The two sides are summed and projected
+ * back with the right eigenvectors.
+ *
+ *   U     : [nf][z][y][x] input state (device).
+ *   Fhat  : [nf][...] output with the `axis` extent n_axis + 1; face j lies
+ *           between cells j-1 and j (for periodic axes face n_axis equals
+ *           face 0 and both are written).
+ *   flags : nullable; [2][nf][faces] uint8 (side 0 = f+, 1 = f-), bit k set
+ *           iff candidate S_k was classified smooth (delta_k = 1).
+ *   C_T   : cutoff, >= 0 (C_T = 0 makes every candidate smooth).
+ *   gamma : ratio of specific heats (> 1; ignored by the scalar system).
+ */
+int tenom_reconstruct_faces(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma,
+                            int axis, const double* U, double* Fhat, uint8_t* flags, void* stream);
+
+/*
+ * Semi-discrete right-hand side (Eq. approximateEq, dimension by dimension):
+ *   dUdt = -sum_axis (Fhat_{i+1/2} - Fhat_{i-1/2}) / dx_axis
+ * accumulated in the axis order x, y, z.  Needs no workspace.
+ *   U    : [nf][z][y][x] input (device);  dUdt : same shape, output.
+ */
+int tenom_flux_divergence(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma,
+                          const double* U, double* dUdt, void* stream);
+
+/*
+ * One third-order SSP Runge-Kutta step of size dt, in place (Sec. 4, after
+ * Gottlieb & Shu):
+ *   U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));
+ *   U <- 1/3 U + 2/3 (U2 + dt L(U2)),
+ * with L = tenom_flux_divergence.  The stage states and the right-hand-side
+ * accumulator live in the caller's workspace `ws` (device memory of at
+ * least tenom_workspace_bytes(grid, scheme) bytes, 256-byte aligned).
+ */
+int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                   double* U, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes tenom_rk3_step needs for this grid (0 if invalid). */
+size_t tenom_workspace_bytes(const tenom_grid* grid, int scheme);
+
+/*
+ * Largest signal rate over the cells: max_cells sum_d (|u_d| + c) / dx_d
+ * (scalar system: sum_d |a_d| / dx_d).  A step at CFL number sigma is
+ * dt = sigma / *out_host.  Synchronises `stream`; a NaN in U yields NaN.
+ */
+int tenom_max_wave_speed(const tenom_grid* grid, double gamma, const double* U, double* out_host,
+                         void* stream);
+
+/* TENOM_OK if every value of U is finite, else TENOM_ENONFINITE.
+ * Synchronises `stream`. */
+int tenom_check_finite(const tenom_grid* grid, const double* U, void* stream);
+
+/* ---- diagnostics -------------------------------------------------------- */
+
+/* Static text for a return code. */
+const char* tenom_strerror(int code);
+/* Message of the last failure on the calling thread ("" if none). */
+const char* tenom_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int tenom_version(void);
+
+/*
+ * Kernel timing: while enabled, every kernel the compute calls launch is
+ * bracketed by HIP events recorded on the same stream.  tenom_profile_read
+ * synchronises those events and returns, per kernel kind, the number of
+ * launches and their summed duration in milliseconds since the last reset.
+ * Kinds: 0 face fluxes (reconstruct_faces), 1 x-sweep, 2 y-sweep,
+ * 3 z-sweep.  At most 4096 launches are recorded between reads.
+ */
+#define TENOM_KERNEL_KINDS 4
+int tenom_profile_enable(int on);
+int tenom_profile_read(int64_t* counts, double* total_ms, int nkinds);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TENOM_H */

@@ -1,0 +1,247 @@
+"""tenom: TENO-M per-face reconstruction on AMD MI355X (gfx950).
+
+Thin ctypes binding of libtenom.so (C ABI in include/tenom.h).  Every step
+of the computation runs in the library's HIP kernels; this module only
+checks tensors, marshals arguments and passes torch's current HIP stream.
+PyTorch provides device memory and streams.  If the library is missing the
+import of any compute call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtenom.so")
+
+# identifiers (include/tenom.h)
+OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+SYS_SCALAR, SYS_EULER = 0, 1
+SCHEME_6, SCHEME_8 = 6, 8
+LIM_MP, LIM_TVD_MINMOD, LIM_TVD5 = 1, 2, 3
+KERNEL_KINDS = ("faces", "sweep_x", "sweep_y", "sweep_z")
+
+SYMBOLS = (
+    "tenom_num_fields", "tenom_reconstruct_faces", "tenom_flux_divergence", "tenom_rk3_step",
+    "tenom_workspace_bytes", "tenom_max_wave_speed", "tenom_check_finite", "tenom_strerror",
+    "tenom_last_error", "tenom_version", "tenom_profile_enable", "tenom_profile_read",
+)
+
+
+class TenomError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tenom error {code}: {msg}")
+        self.code = code
+
+
+class _CGrid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("dx", C.c_double * 3),
+                ("bc", C.c_int32 * 3), ("system", C.c_int32), ("adv", C.c_double * 3)]
+
+
+@dataclass
+class Grid:
+    """Uniform Cartesian grid: n and dx in x, y, z order, one entry per axis."""
+    ndim: int
+    n: Sequence[int]
+    dx: Sequence[float]
+    bc: Sequence[int] = field(default_factory=lambda: (BC_PERIODIC,) * 3)
+    system: int = SYS_EULER
+    adv: Sequence[float] = (0.0, 0.0, 0.0)
+
+    @classmethod
+    def of(cls, g) -> "Grid":
+        if isinstance(g, Grid):
+            return g
+        nd = int(g["ndim"])
+        return cls(ndim=nd, n=tuple(g["n"]), dx=tuple(g.get("dx", [1.0] * nd)),
+                   bc=tuple(g.get("bc", [0] * nd)), system=int(g.get("system", SYS_EULER)),
+                   adv=tuple(g.get("adv", [0.0] * nd)))
+
+    def to_c(self) -> _CGrid:
+        c = _CGrid()
+        c.ndim = int(self.ndim)
+        for d in range(3):
+            c.n[d] = int(self.n[d]) if d < self.ndim else 1
+            c.dx[d] = float(self.dx[d]) if d < len(self.dx) else 1.0
+            c.bc[d] = int(self.bc[d]) if d < len(self.bc) else 0
+            c.adv[d] = float(self.adv[d]) if d < len(self.adv) else 0.0
+        c.system = int(self.system)
+        return c
+
+    @property
+    def nfields(self) -> int:
+        return 1 if self.system == SYS_SCALAR else self.ndim + 2
+
+    def state_shape(self):
+        return (self.nfields,) + tuple(int(v) for v in reversed(list(self.n)[: self.ndim]))
+
+    def face_shape(self, axis: int):
+        n = [int(v) for v in list(self.n)[: self.ndim]]
+        n[axis] += 1
+        return (self.nfields,) + tuple(reversed(n))
+
+
+_lib = None
+
+
+def build_library(verbose: bool = False) -> str:
+    """Compile libtenom.so in-tree (hipcc, gfx950)."""
+    from . import build as _build
+    return _build.build(verbose=verbose)
+
+
+def lib() -> C.CDLL:
+    """Load libtenom.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2010_13289_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        gp, vp, dp = C.POINTER(_CGrid), C.c_void_p, C.c_double
+        L.tenom_num_fields.argtypes = [gp]
+        L.tenom_reconstruct_faces.argtypes = [gp, C.c_int, C.c_int, dp, dp, C.c_int, vp, vp, vp, vp]
+        L.tenom_flux_divergence.argtypes = [gp, C.c_int, C.c_int, dp, dp, vp, vp, vp]
+        L.tenom_rk3_step.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, C.c_size_t, vp]
+        L.tenom_workspace_bytes.argtypes = [gp, C.c_int]
+        L.tenom_workspace_bytes.restype = C.c_size_t
+        L.tenom_max_wave_speed.argtypes = [gp, dp, vp, C.POINTER(C.c_double), vp]
+        L.tenom_check_finite.argtypes = [gp, vp, vp]
+        L.tenom_strerror.argtypes = [C.c_int]
+        L.tenom_strerror.restype = C.c_char_p
+        L.tenom_last_error.restype = C.c_char_p
+        L.tenom_profile_enable.argtypes = [C.c_int]
+        L.tenom_profile_read.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = lib().tenom_last_error().decode() or lib().tenom_strerror(rc).decode()
+        raise TenomError(rc, msg)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _state(U, grid: Grid, name="U"):
+    import torch
+    if not isinstance(U, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if U.dtype != torch.float64 or not U.is_cuda or not U.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor on a HIP device")
+    if tuple(U.shape) != grid.state_shape():
+        raise ValueError(f"{name} has shape {tuple(U.shape)}, expected {grid.state_shape()}")
+    return C.c_void_p(U.data_ptr())
+
+
+def reconstruct_faces(U, grid, scheme: int, limiter: int, C_T: float, gamma: float, axis: int,
+                      return_flags: bool = False, out=None, stream=None):
+    """Face fluxes of one axis (shape of U with n_axis + 1 along the axis);
+    with return_flags also the [2, nf, faces...] uint8 smoothness flags."""
+    import torch
+    g = Grid.of(grid)
+    ptr = _state(U, g)
+    fshape = g.face_shape(axis) if 0 <= axis < g.ndim else None
+    if fshape is None:
+        raise TenomError(EINVAL, f"axis {axis} out of range")
+    if out is None:
+        out = torch.empty(fshape, dtype=torch.float64, device=U.device)
+    elif tuple(out.shape) != fshape or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out has the wrong shape, dtype or layout")
+    flags = torch.empty((2,) + fshape, dtype=torch.uint8, device=U.device) if return_flags else None
+    gc = g.to_c()
+    _check(lib().tenom_reconstruct_faces(C.byref(gc), scheme, limiter, C_T, gamma, axis, ptr,
+                                         C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(flags.data_ptr()) if flags is not None else None,
+                                         _stream(stream)))
+    return (out, flags) if return_flags else out
+
+
+def flux_divergence(U, grid, scheme: int, limiter: int, C_T: float, gamma: float, out=None, stream=None):
+    """dU/dt = -sum_axis dF/dx (same shape as U)."""
+    import torch
+    g = Grid.of(grid)
+    ptr = _state(U, g)
+    if out is None:
+        out = torch.empty_like(U)
+    optr = _state(out, g, "out")
+    gc = g.to_c()
+    _check(lib().tenom_flux_divergence(C.byref(gc), scheme, limiter, C_T, gamma, ptr, optr, _stream(stream)))
+    return out
+
+
+def workspace_bytes(grid, scheme: int) -> int:
+    g = Grid.of(grid).to_c()
+    return int(lib().tenom_workspace_bytes(C.byref(g), scheme))
+
+
+class Workspace:
+    """Device workspace for rk3_step, owned by a torch uint8 tensor."""
+
+    def __init__(self, grid, scheme: int, device="cuda"):
+        import torch
+        nbytes = workspace_bytes(grid, scheme)
+        if nbytes == 0:
+            raise TenomError(EINVAL, "invalid grid or scheme for a workspace")
+        # torch's caching allocator returns >= 256-byte aligned blocks
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+
+def rk3_step(U, grid, scheme: int, limiter: int, C_T: float, gamma: float, dt: float,
+             workspace: Workspace | None = None, stream=None):
+    """One SSP-RK3 step in place on U; returns U."""
+    g = Grid.of(grid)
+    ptr = _state(U, g)
+    ws = workspace if workspace is not None else Workspace(g, scheme, U.device)
+    gc = g.to_c()
+    _check(lib().tenom_rk3_step(C.byref(gc), scheme, limiter, C_T, gamma, dt, ptr, ws.ptr, ws.nbytes,
+                                _stream(stream)))
+    return U
+
+
+def max_wave_speed(U, grid, gamma: float, stream=None) -> float:
+    """max over cells of sum_d (|u_d| + c)/dx_d; dt = CFL / this."""
+    g = Grid.of(grid)
+    ptr = _state(U, g)
+    out = C.c_double()
+    gc = g.to_c()
+    _check(lib().tenom_max_wave_speed(C.byref(gc), gamma, ptr, C.byref(out), _stream(stream)))
+    return out.value
+
+
+def check_finite(U, grid, stream=None) -> bool:
+    g = Grid.of(grid)
+    ptr = _state(U, g)
+    gc = g.to_c()
+    rc = lib().tenom_check_finite(C.byref(gc), ptr, _stream(stream))
+    if rc == ENONFINITE:
+        return False
+    _check(rc)
+    return True
+
+
+def profile_enable(on: bool = True):
+    _check(lib().tenom_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{kind: (launches, total_ms)} since the last read (synchronises)."""
+    n = len(KERNEL_KINDS)
+    cnt = (C.c_int64 * n)()
+    ms = (C.c_double * n)()
+    _check(lib().tenom_profile_read(cnt, ms, n))
+    return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(KERNEL_KINDS)}

@@ -1,0 +1,92 @@
+"""Build libtenom.so (HIP, gfx950) in-tree.
+
+Steps: regenerate csrc/teno_tables.h from gen_tables.py, compile the eight
+instantiation units (fields x K) and the C-ABI layer in parallel with hipcc,
+link them into paper_2010_13289_amd/libtenom.so.
+
+    python -m paper_2010_13289_amd.build [--verbose]
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libtenom.so")
+ARCH = os.environ.get("TENOM_OFFLOAD_ARCH", "gfx950")
+
+HIPCC_FLAGS = [
+    f"--offload-arch={ARCH}",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-Wall",
+    "-Wno-unused-result",
+    # no packed FP32 instructions anywhere in the device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+UNITS = [(nf, k) for nf in (1, 3, 4, 5) for k in (6, 8)]
+
+
+def _hipcc() -> str:
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cand = os.path.join(rocm, "bin", "hipcc")
+    return cand if os.path.exists(cand) else "hipcc"
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"command failed ({r.returncode}): {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose and (r.stdout or r.stderr):
+        print(r.stdout + r.stderr, flush=True)
+    return r
+
+
+def generate_tables():
+    sys.path.insert(0, CSRC)
+    try:
+        import gen_tables  # noqa: WPS433
+    finally:
+        sys.path.pop(0)
+    path = os.path.join(CSRC, "teno_tables.h")
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        gen_tables.main(fh)
+    os.replace(tmp, path)
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile and link libtenom.so; returns its path.  Always rebuilds."""
+    os.makedirs(BUILD, exist_ok=True)
+    generate_tables()
+    hipcc = _hipcc()
+    cmds = []
+    objs = []
+    for nf, k in UNITS:
+        obj = os.path.join(BUILD, f"inst_nf{nf}_k{k}.o")
+        objs.append(obj)
+        cmds.append([hipcc, *HIPCC_FLAGS, f"-DTENOM_NF={nf}", f"-DTENOM_K={k}", "-c",
+                     os.path.join(CSRC, "tenom_inst.hip"), "-o", obj])
+    obj = os.path.join(BUILD, "tenom_abi.o")
+    objs.append(obj)
+    cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "tenom_abi.hip"), "-o", obj])
+    if jobs is None:
+        jobs = int(os.environ.get("MAX_JOBS", "0") or 0) or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    tmp = LIB + ".tmp"
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="--verbose" in sys.argv))

@@ -1,0 +1,311 @@
+// Device code of the TENO-M face reconstruction for gfx950 (FP64 throughout).
+//
+// One thread computes the complete numerical flux of one face: K cell
+// states along the sweep axis -> (Euler) Roe-average characteristic
+// projection and Rusanov splitting -> two mirrored TENO-M reconstructions
+// per characteristic field -> back-projection.  Everything stays in
+// registers; there is no matrix-shaped work worth MFMA (each face has its
+// own 5x5 eigenvector basis, and FP64 MFMA is no faster than FP64 VALU).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "teno_tables.h"
+
+namespace tenom {
+
+// Eq. measureTENO: gamma_k = (C + tau_K / (beta_k + eps))^q, C = 1, q = 6
+constexpr double kEps = 1e-40;
+
+// Limiter identifiers of the C ABI (values of TENOM_LIM_*).
+enum : int { LIM_MP = 1, LIM_TVD_MINMOD = 2, LIM_TVD5 = 3 };
+
+// minmod of two / four arguments (Eqs. minmod222, minmod444), branch-free:
+// the smallest-magnitude argument if all share a sign, else 0.
+__device__ __forceinline__ double minmod2(double x, double y) {
+  return fmax(fmin(x, y), 0.0) + fmin(fmax(x, y), 0.0);
+}
+__device__ __forceinline__ double minmod4(double a, double b, double c, double d) {
+  const double lo = fmin(fmin(a, b), fmin(c, d));
+  const double hi = fmax(fmax(a, b), fmax(c, d));
+  return fmax(lo, 0.0) + fmin(hi, 0.0);
+}
+
+// 1/x from the hardware estimate plus two Newton-Raphson steps (relative
+// error at the level of the last bit for normal x).
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// ---------------------------------------------------------------------------
+// One TENO-M reconstruction at x_{i+1/2} from v[0..K-1] = f_{i-K/2+1..i+K/2}
+// (Secs. 2.2-3.3).  Computed relative to v_i, in differences of adjacent
+// values.  `bits` receives delta_k (1 = smooth) in bit k when FLAGS.
+// ---------------------------------------------------------------------------
+template <int K, int LIM, bool FLAGS>
+__device__ __forceinline__ double teno_m(const double (&v)[K], double C_T, uint32_t& bits) {
+  using T = TenoTables<K>;
+  constexpr int NK = K - 2;
+  constexpr int C0 = K / 2 - 1;  // index of v_i
+
+  double D[K - 1];
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) D[j] = v[j + 1] - v[j];
+
+  // candidate fluxes (Table 1), minus v_i
+  double c[NK];
+  T::candidates(D, c);
+
+  // smoothness indicators and the global tau_K (Eqs. measureTENO, taukTENO)
+  double beta[NK], betaK;
+  T::betas(D, beta, betaK);
+  const double tau = fabs(betaK - (beta[1] + beta[2] + 4.0 * beta[0]) * (1.0 / 6.0));
+
+  // gamma_k and the cutoff: chi_k = gamma_k / sum < C_T  <=>  gamma_k < C_T sum
+  double g[NK];
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const double s = fma(tau, rcp(beta[k] + kEps), 1.0);
+    const double s2 = s * s;
+    g[k] = s2 * s2 * s2;
+    sum += g[k];
+  }
+  const double thr = C_T * sum;
+
+  // limiter on the nonsmooth candidates (Eq. mp_flux), relative to v_i
+  const double dm = D[C0 - 1];  // f_i - f_{i-1}
+  const double dp = D[C0];      // f_{i+1} - f_i
+  double lo = 0.0, hi = 0.0, ftvd = 0.0;
+  if constexpr (LIM == LIM_MP) {
+    // curvatures (Eq. curvature) and d^M4 at i -+ 1/2 (Eq. maximal_curvature)
+    const double d_im1 = D[C0 - 1] - D[C0 - 2];
+    const double d_i = D[C0] - D[C0 - 1];
+    const double d_ip1 = D[C0 + 1] - D[C0];
+    const double dR = minmod4(4.0 * d_i - d_ip1, 4.0 * d_ip1 - d_i, d_i, d_ip1);
+    const double dL = minmod4(4.0 * d_im1 - d_i, 4.0 * d_i - d_im1, d_im1, d_i);
+    // Eqs. upper_limiter, median_value, large_curvature (alpha 1.25, beta 4)
+    const double ul = 1.25 * dm;
+    const double md = 0.5 * dp - 0.5 * dR;
+    const double lc = fma(4.0 / 3.0, dL, 0.5 * dm);
+    // Eq. value_min_max; 0 (= f_i) lies in both brackets, so lo <= 0 <= hi
+    lo = fmax(fmin(fmin(0.0, dp), md), fmin(fmin(0.0, ul), lc));
+    hi = fmin(fmax(fmax(0.0, dp), md), fmax(fmax(0.0, ul), lc));
+  } else if constexpr (LIM == LIM_TVD_MINMOD) {
+    ftvd = 0.5 * minmod2(dm, dp);
+  } else if constexpr (LIM == LIM_TVD5) {
+    // Eqs. high order TVD, TVDhighorder2, TVDbeta multiplied through by
+    // delta^- (division-free; equal wherever the slope ratios exist)
+    const double B = (-2.0 * D[C0 - 2] + 11.0 * dm + 24.0 * dp - 3.0 * D[C0 + 1]) * (1.0 / 30.0);
+    const double up = fmax(0.0, fmin(fmin(2.0 * dm, 2.0 * dp), B));
+    const double dn = fmin(0.0, fmax(fmax(2.0 * dm, 2.0 * dp), B));
+    ftvd = 0.5 * (dm > 0.0 ? up : (dm < 0.0 ? dn : 0.0));
+  }
+
+  // assembly with the optimal weights, no renormalisation (Eq. reconstuction)
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const bool smooth = !(g[k] < thr);
+    double lim;
+    if constexpr (LIM == LIM_MP) {
+      lim = fmin(fmax(c[k], lo), hi);  // median(f_k, f_min, f_max), lo <= hi
+    } else {
+      lim = ftvd;
+    }
+    acc = fma(T::d(k), smooth ? c[k] : lim, acc);
+    if constexpr (FLAGS) bits |= (smooth ? 1u : 0u) << k;
+  }
+  return v[C0] + acc;
+}
+
+// ---------------------------------------------------------------------------
+// Addressing of the K stencil cells of face j along one axis.
+// ---------------------------------------------------------------------------
+struct Line {
+  long base;    // linear index of the line's cell 0
+  long stride;  // index step along the axis
+  int n;        // cells along the axis
+  int bc;       // 0 periodic, 1 transmissive
+};
+
+// cell index of axis position jj (|jj| < 2n for periodic) under the rule
+__device__ __forceinline__ long cell_at(const Line& L, int jj) {
+  int q;
+  if (L.bc == 0) {
+    q = jj < 0 ? jj + L.n : (jj >= L.n ? jj - L.n : jj);
+  } else {
+    q = jj < 0 ? 0 : (jj >= L.n ? L.n - 1 : jj);
+  }
+  return L.base + (long)q * L.stride;
+}
+
+// ---------------------------------------------------------------------------
+// Scalar advection face flux: f = a u, Rusanov split with alpha = |a|.
+// ---------------------------------------------------------------------------
+template <int K, int LIM, bool FLAGS>
+__device__ __forceinline__ void scalar_face(const double* __restrict__ U, const Line& L, int j, double a,
+                                            double C_T, double& F, uint32_t (&bits)[2]) {
+  const double alpha = fabs(a);
+  double vp[K], vm[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    const double u = U[cell_at(L, j - K / 2 + m)];
+    const double f = a * u;
+    vp[m] = 0.5 * fma(alpha, u, f);
+    vm[K - 1 - m] = 0.5 * fma(-alpha, u, f);  // mirrored for the f- side
+  }
+  bits[0] = bits[1] = 0u;
+  F = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1]);
+}
+
+// ---------------------------------------------------------------------------
+// Euler face flux.  NF = ndim + 2 fields, handled in a frame rotated so that
+// component 1 is the momentum normal to the face: fld[q] is the storage
+// field of rotated component q.  Characteristic fields are ordered
+// (u_n - c, entropy, shear waves in ascending axis order, u_n + c).
+// ---------------------------------------------------------------------------
+template <int NF, int K, int LIM, bool FLAGS>
+__device__ __forceinline__ void euler_face(const double* __restrict__ U, long N, const int (&fld)[NF],
+                                           const Line& L, int j, double gamma, double C_T, double (&Fh)[NF],
+                                           uint32_t (&bits)[2][NF]) {
+  constexpr int ND = NF - 2;
+  constexpr int C0 = K / 2 - 1;
+  const double gm1 = gamma - 1.0;
+
+  // Roe average of cells i = j-1 and i+1 = j
+  double ut[ND], Ht, ct;
+  {
+    double rs[2], vel[2][ND], H[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const long cell = cell_at(L, j - 1 + s);
+      const double rho = U[cell];
+      const double rinv = rcp(rho);
+      double q2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        vel[s][d] = U[fld[1 + d] * N + cell] * rinv;
+        q2 = fma(vel[s][d], vel[s][d], q2);
+      }
+      const double E = U[fld[NF - 1] * N + cell];
+      const double p = gm1 * fma(-0.5 * rho, q2, E);
+      H[s] = (E + p) * rinv;
+      rs[s] = sqrt(rho);
+    }
+    const double w = rcp(rs[0] + rs[1]);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) ut[d] = (rs[0] * vel[0][d] + rs[1] * vel[1][d]) * w;
+    Ht = (rs[0] * H[0] + rs[1] * H[1]) * w;
+    double q2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) q2 = fma(ut[d], ut[d], q2);
+    ct = sqrt(gm1 * fma(-0.5, q2, Ht));
+  }
+  const double cinv = rcp(ct);
+  const double b1 = gm1 * cinv * cinv;
+  double q2t = 0.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) q2t = fma(ut[d], ut[d], q2t);
+  const double b2 = 0.5 * q2t * b1;
+
+  // left eigenvectors applied to a conservative vector X
+  auto project = [&](const double (&X)[NF], double (&w)[NF]) {
+    double um = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) um = fma(ut[d], X[1 + d], um);
+    const double A = fma(b2, X[0], b1 * (X[NF - 1] - um));
+    const double B = fma(ut[0], X[0], -X[1]) * cinv;
+    w[0] = 0.5 * (A + B);
+    w[1] = X[0] - A;
+#pragma unroll
+    for (int t = 1; t < ND; ++t) w[1 + t] = fma(-ut[t], X[0], X[1 + t]);
+    w[NF - 1] = 0.5 * (A - B);
+  };
+
+  // stencil cells: physical flux, signal speed, characteristic projections
+  double W[K][NF], G[K][NF];
+  double alpha = 0.0;
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    const long cell = cell_at(L, j - K / 2 + m);
+    double X[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) X[q] = U[fld[q] * N + cell];
+    const double rinv = rcp(X[0]);
+    const double un = X[1] * rinv;
+    double mu = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) mu = fma(X[1 + d], X[1 + d], mu);
+    const double p = gm1 * fma(-0.5 * rinv, mu, X[NF - 1]);
+    double F[NF];
+    F[0] = X[1];
+    F[1] = fma(X[1], un, p);
+#pragma unroll
+    for (int t = 1; t < ND; ++t) F[1 + t] = X[1 + t] * un;
+    F[NF - 1] = (X[NF - 1] + p) * un;
+    const double c = sqrt(gamma * p * rinv);
+    alpha = fmax(alpha, fabs(un) + c);
+    project(X, W[m]);
+    project(F, G[m]);
+  }
+
+  // Rusanov split and two mirrored TENO-M reconstructions per field
+  double fc[NF];
+#pragma unroll
+  for (int q = 0; q < NF; ++q) {
+    double vp[K], vm[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      vp[m] = 0.5 * fma(alpha, W[m][q], G[m][q]);
+      vm[K - 1 - m] = 0.5 * fma(-alpha, W[m][q], G[m][q]);
+    }
+    bits[0][q] = bits[1][q] = 0u;
+    fc[q] = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0][q]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1][q]);
+  }
+  (void)C0;
+
+  // back to conservative variables with the right eigenvectors
+  const double s = fc[0] + fc[1] + fc[NF - 1];
+  const double dlr = fc[NF - 1] - fc[0];
+  Fh[0] = s;
+  Fh[1] = fma(ut[0], s, ct * dlr);
+  double e = fma(Ht, fc[0] + fc[NF - 1], ut[0] * ct * dlr);
+  e = fma(0.5 * q2t, fc[1], e);
+#pragma unroll
+  for (int t = 1; t < ND; ++t) {
+    Fh[1 + t] = fma(ut[t], s, fc[1 + t]);
+    e = fma(ut[t], fc[1 + t], e);
+  }
+  Fh[NF - 1] = e;
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch on the system: NF == 1 is scalar advection, otherwise Euler.
+// ---------------------------------------------------------------------------
+struct FaceParams {
+  double gamma;
+  double C_T;
+  double adv;  // advection speed along the axis (scalar system)
+};
+
+template <int NF, int K, int LIM, bool FLAGS>
+__device__ __forceinline__ void face_flux(const double* __restrict__ U, long N, const int (&fld)[NF],
+                                          const Line& L, int j, const FaceParams& fp, double (&F)[NF],
+                                          uint32_t (&bits)[2][NF]) {
+  if constexpr (NF == 1) {
+    uint32_t b[2];
+    scalar_face<K, LIM, FLAGS>(U, L, j, fp.adv, fp.C_T, F[0], b);
+    bits[0][0] = b[0];
+    bits[1][0] = b[1];
+  } else {
+    euler_face<NF, K, LIM, FLAGS>(U, N, fld, L, j, fp.gamma, fp.C_T, F, bits);
+  }
+}
+
+}  // namespace tenom

@@ -1,0 +1,506 @@
+// C-ABI layer of libtenom: argument checks, workspace layout, the sweep
+// schedule of the flux divergence and the SSP-RK3 step, the wave-speed
+// reduction, and optional per-kernel timing.  See include/tenom.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/tenom.h"
+#include "dispatch.h"
+
+using namespace tenom;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(TENOM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int nfields(const tenom_grid* g) {
+  if (!g) return 0;
+  if (g->system == TENOM_SYS_SCALAR) return 1;
+  if (g->system == TENOM_SYS_EULER && g->ndim >= 1 && g->ndim <= 3) return g->ndim + 2;
+  return 0;
+}
+
+struct Dims {
+  int nx, ny, nz;
+  long N;
+};
+
+Dims dims(const tenom_grid* g) {
+  Dims d{g->n[0], g->ndim > 1 ? g->n[1] : 1, g->ndim > 2 ? g->n[2] : 1, 0};
+  d.N = (long)d.nx * d.ny * d.nz;
+  return d;
+}
+
+int check_grid(const tenom_grid* g, int K) {
+  if (!g) return fail(TENOM_EINVAL, "grid is NULL");
+  if (g->ndim < 1 || g->ndim > 3) return fail(TENOM_EINVAL, "ndim %d not in {1,2,3}", g->ndim);
+  if (g->system != TENOM_SYS_SCALAR && g->system != TENOM_SYS_EULER)
+    return fail(TENOM_EUNSUPPORTED, "unknown system %d", g->system);
+  long cells = 1;
+  for (int d = 0; d < g->ndim; ++d) {
+    if (g->n[d] < K) return fail(TENOM_EINVAL, "axis %d has %d cells, fewer than K = %d", d, g->n[d], K);
+    if (!(g->dx[d] > 0.0) || !isfinite(g->dx[d])) return fail(TENOM_EINVAL, "dx[%d] must be finite and > 0", d);
+    if (g->bc[d] != TENOM_BC_PERIODIC && g->bc[d] != TENOM_BC_TRANSMISSIVE)
+      return fail(TENOM_EINVAL, "bc[%d] = %d is not a boundary rule", d, g->bc[d]);
+    if (g->system == TENOM_SYS_SCALAR && !isfinite(g->adv[d]))
+      return fail(TENOM_EINVAL, "adv[%d] must be finite", d);
+    cells *= g->n[d];
+    if (cells > (1L << 31) - 1) return fail(TENOM_EINVAL, "grid has more than 2^31-1 cells");
+  }
+  return TENOM_OK;
+}
+
+int check_scheme(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma) {
+  if (scheme != TENOM_SCHEME_6 && scheme != TENOM_SCHEME_8)
+    return fail(TENOM_EUNSUPPORTED, "unknown scheme %d (use 6 or 8)", scheme);
+  if (limiter != TENOM_LIM_MP && limiter != TENOM_LIM_TVD_MINMOD && limiter != TENOM_LIM_TVD5)
+    return fail(TENOM_EUNSUPPORTED, "unknown limiter %d", limiter);
+  int rc = check_grid(g, scheme);
+  if (rc) return rc;
+  if (!(C_T >= 0.0)) return fail(TENOM_EINVAL, "C_T must be >= 0 (got %g)", C_T);
+  if (g->system == TENOM_SYS_EULER && !(gamma > 1.0 && isfinite(gamma)))
+    return fail(TENOM_EINVAL, "gamma must be finite and > 1 (got %g)", gamma);
+  return TENOM_OK;
+}
+
+// rotated component q -> storage field, for the sweep axis
+void field_map(const tenom_grid* g, int axis, int (&fld)[5]) {
+  for (int q = 0; q < 5; ++q) fld[q] = 0;
+  if (g->system == TENOM_SYS_SCALAR) return;
+  const int nd = g->ndim;
+  fld[0] = 0;
+  fld[1] = 1 + axis;
+  int q = 2;
+  for (int t = 0; t < nd; ++t)
+    if (t != axis) fld[q++] = 1 + t;
+  fld[nd + 1] = nd + 1;
+}
+
+FaceParams face_params(const tenom_grid* g, int axis, double C_T, double gamma) {
+  FaceParams fp;
+  fp.gamma = gamma;
+  fp.C_T = C_T;
+  fp.adv = (g->system == TENOM_SYS_SCALAR) ? g->adv[axis] : 0.0;
+  return fp;
+}
+
+using FacesFn = hipError_t (*)(int, const FacesLaunch&);
+using SweepFn = hipError_t (*)(int, const SweepLaunch&);
+
+bool pick(int nf, int K, FacesFn* f, SweepFn* s) {
+#define TENOM_CASE(NF, KK)                      \
+  if (nf == NF && K == KK) {                    \
+    *f = tenom_faces_nf##NF##_k##KK;            \
+    *s = tenom_sweep_nf##NF##_k##KK;            \
+    return true;                                \
+  }
+  TENOM_CASE(1, 6)
+  TENOM_CASE(1, 8)
+  TENOM_CASE(3, 6)
+  TENOM_CASE(3, 8)
+  TENOM_CASE(4, 6)
+  TENOM_CASE(4, 8)
+  TENOM_CASE(5, 6)
+  TENOM_CASE(5, 8)
+#undef TENOM_CASE
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+};
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<hipEvent_t> g_event_pool;
+std::vector<ProfRec> g_prof_recs;
+constexpr size_t kMaxProf = 4096;
+
+hipEvent_t pool_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on = false;
+  ProfScope(int k, hipStream_t st) : kind(k), s(st) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on || g_prof_recs.size() >= kMaxProf) return;
+    a = pool_event();
+    b = pool_event();
+    if (!a || !b) return;
+    on = hipEventRecord(a, s) == hipSuccess;
+  }
+  ~ProfScope() {
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (hipEventRecord(b, s) == hipSuccess) g_prof_recs.push_back(ProfRec{kind, a, b});
+  }
+};
+
+int march_segment(int n, int nx, int n_other) {
+  static int env = -1;
+  if (env < 0) {
+    const char* s = getenv("TENOM_MARCH_SEG");
+    env = s ? atoi(s) : 0;
+    if (env < 0) env = 0;
+  }
+  if (env > 0) return env;
+  // aim for >= 4096 waves (two full rounds at two waves per SIMD on 256
+  // CUs) while keeping the one redundant face per segment below ~3%
+  const long waves_per_set = (long)((nx + 63) / 64) * n_other;
+  long nseg = (4096 + waves_per_set - 1) / waves_per_set;
+  if (nseg < 1) nseg = 1;
+  long seg = (n + nseg - 1) / nseg;
+  if (seg < 32) seg = (n < 32) ? n : 32;
+  return (int)seg;
+}
+
+// Launch one sweep of `axis` with the given epilogue.
+int sweep(const tenom_grid* g, int K, int limiter, double C_T, double gamma, int axis, const double* U, double* R,
+          const double* U0, const double* Us, double* Uout, double a, double b, double dt, int mode,
+          hipStream_t stream) {
+  FacesFn ff;
+  SweepFn sf;
+  const int nf = nfields(g);
+  if (!pick(nf, K, &ff, &sf)) return fail(TENOM_EUNSUPPORTED, "no kernel for %d fields, K = %d", nf, K);
+  const Dims d = dims(g);
+  SweepLaunch L;
+  L.axis = axis;
+  L.U = U;
+  L.R = R;
+  L.U0 = U0;
+  L.Us = Us;
+  L.Uout = Uout;
+  L.a = a;
+  L.b = b;
+  L.dt = dt;
+  L.mode = mode;
+  L.nx = d.nx;
+  L.ny = d.ny;
+  L.nz = d.nz;
+  L.bc = g->bc[axis];
+  L.inv_dx = 1.0 / g->dx[axis];
+  const int n_axis = axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
+  L.seg = axis == 0 ? 0 : march_segment(n_axis, d.nx, axis == 1 ? d.nz : d.ny);
+  field_map(g, axis, L.fld);
+  L.fp = face_params(g, axis, C_T, gamma);
+  L.stream = stream;
+  hipError_t e;
+  {
+    ProfScope ps(1 + axis, stream);
+    e = sf(limiter, L);
+  }
+  if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  return TENOM_OK;
+}
+
+// small per-device buffer for the reductions
+std::mutex g_red_mu;
+void* g_red_buf[64] = {nullptr};
+
+int reduction_buffer(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(TENOM_EHIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_red_mu);
+  if (!g_red_buf[dev]) {
+    e = hipMalloc(&g_red_buf[dev], 16);
+    if (e != hipSuccess) {
+      g_red_buf[dev] = nullptr;
+      return hip_fail(e, "hipMalloc reduction buffer");
+    }
+  }
+  *out = g_red_buf[dev];
+  return TENOM_OK;
+}
+
+// max over cells of sum_d (|u_d| + c)/dx_d, as the ordered bit pattern of a
+// non-negative double (NaN patterns order above every finite value)
+__global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ U, long N, int ndim, int system,
+                                                    double gamma, double ix0, double ix1, double ix2, double a0,
+                                                    double a1, double a2, unsigned long long* out) {
+  double best = 0.0;
+  bool nan = false;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+    double s;
+    if (system == TENOM_SYS_SCALAR) {
+      s = fabs(a0) * ix0 + (ndim > 1 ? fabs(a1) * ix1 : 0.0) + (ndim > 2 ? fabs(a2) * ix2 : 0.0);
+    } else {
+      const double rho = U[i];
+      const double ri = 1.0 / rho;
+      double vel[3] = {0.0, 0.0, 0.0}, q2 = 0.0;
+      for (int d = 0; d < ndim; ++d) {
+        vel[d] = U[(1 + d) * N + i] * ri;
+        q2 += vel[d] * vel[d];
+      }
+      const double p = (gamma - 1.0) * (U[(ndim + 1) * N + i] - 0.5 * rho * q2);
+      const double c = sqrt(gamma * p * ri);
+      s = (fabs(vel[0]) + c) * ix0;
+      if (ndim > 1) s += (fabs(vel[1]) + c) * ix1;
+      if (ndim > 2) s += (fabs(vel[2]) + c) * ix2;
+    }
+    if (s != s) nan = true;
+    best = fmax(best, s);
+  }
+  unsigned long long bits = nan ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(best);
+  // wave then block reduction of the unsigned ordering
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_down(bits, off, 64);
+    bits = o > bits ? o : bits;
+  }
+  __shared__ unsigned long long part[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = bits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = part[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = part[w] > m ? part[w] : m;
+    atomicMax(out, m);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ U, long M, unsigned int* out) {
+  bool bad = false;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (long)gridDim.x * blockDim.x)
+    bad |= !isfinite(U[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(out, 1u);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int tenom_num_fields(const tenom_grid* grid) { return nfields(grid); }
+
+const char* tenom_strerror(int code) {
+  switch (code) {
+    case TENOM_OK: return "success";
+    case TENOM_EINVAL: return "invalid argument";
+    case TENOM_EUNSUPPORTED: return "unsupported scheme, limiter or system";
+    case TENOM_EWORKSPACE: return "workspace too small";
+    case TENOM_EHIP: return "HIP runtime error";
+    case TENOM_ENONFINITE: return "non-finite value";
+    default: return "unknown error";
+  }
+}
+
+const char* tenom_last_error(void) { return g_err; }
+
+int tenom_version(void) { return 10000; }
+
+int tenom_reconstruct_faces(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, int axis,
+                            const double* U, double* Fhat, uint8_t* flags, void* stream) {
+  g_err[0] = 0;
+  int rc = check_scheme(grid, scheme, limiter, C_T, gamma);
+  if (rc) return rc;
+  if (axis < 0 || axis >= grid->ndim) return fail(TENOM_EINVAL, "axis %d not in [0, ndim)", axis);
+  if (!U || !Fhat) return fail(TENOM_EINVAL, "U and Fhat must not be NULL");
+  FacesFn ff;
+  SweepFn sf;
+  if (!pick(nfields(grid), scheme, &ff, &sf)) return fail(TENOM_EUNSUPPORTED, "no kernel");
+  const Dims d = dims(grid);
+  FacesLaunch L;
+  L.U = U;
+  L.Fhat = Fhat;
+  L.flags = flags;
+  L.axis = axis;
+  L.nx = d.nx;
+  L.ny = d.ny;
+  L.nz = d.nz;
+  L.bc = grid->bc[axis];
+  field_map(grid, axis, L.fld);
+  L.fp = face_params(grid, axis, C_T, gamma);
+  L.stream = (hipStream_t)stream;
+  hipError_t e;
+  {
+    ProfScope ps(0, L.stream);
+    e = ff(limiter, L);
+  }
+  if (e != hipSuccess) return hip_fail(e, "face kernel launch");
+  return TENOM_OK;
+}
+
+int tenom_flux_divergence(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma,
+                          const double* U, double* dUdt, void* stream) {
+  g_err[0] = 0;
+  int rc = check_scheme(grid, scheme, limiter, C_T, gamma);
+  if (rc) return rc;
+  if (!U || !dUdt) return fail(TENOM_EINVAL, "U and dUdt must not be NULL");
+  if ((const void*)U == (const void*)dUdt) return fail(TENOM_EINVAL, "dUdt must not alias U");
+  hipStream_t s = (hipStream_t)stream;
+  for (int ax = 0; ax < grid->ndim; ++ax) {
+    rc = sweep(grid, scheme, limiter, C_T, gamma, ax, U, dUdt, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0,
+               ax == 0 ? EPI_STORE : EPI_ACCUM, s);
+    if (rc) return rc;
+  }
+  return TENOM_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t tenom_workspace_bytes(const tenom_grid* grid, int scheme) {
+  if (check_grid(grid, scheme == TENOM_SCHEME_8 ? 8 : 6) != TENOM_OK) return 0;
+  if (scheme != TENOM_SCHEME_6 && scheme != TENOM_SCHEME_8) return 0;
+  const size_t state = align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
+  return 3 * state;  // divergence accumulator R, stage states U1 and U2
+}
+
+int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt, double* U,
+                   void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_scheme(grid, scheme, limiter, C_T, gamma);
+  if (rc) return rc;
+  if (!U || !ws) return fail(TENOM_EINVAL, "U and ws must not be NULL");
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(TENOM_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+  if (((uintptr_t)ws & 255) != 0) return fail(TENOM_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = tenom_workspace_bytes(grid, scheme);
+  if (ws_bytes < need) return fail(TENOM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  const size_t state = need / 3;
+  double* R = (double*)ws;
+  double* U1 = (double*)((char*)ws + state);
+  double* U2 = (double*)((char*)ws + 2 * state);
+  hipStream_t s = (hipStream_t)stream;
+  const int nd = grid->ndim;
+  // (a, b) of U_out = a U^n + b (U_s + dt L(U_s)), stage inputs and outputs
+  const double A[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+  const double* Uin[3] = {U, U1, U2};
+  double* Uo[3] = {U1, U2, U};
+  for (int st = 0; st < 3; ++st) {
+    for (int ax = 0; ax < nd; ++ax) {
+      const bool last = (ax == nd - 1);
+      int mode = last ? (nd == 1 ? EPI_RK1 : EPI_RK) : (ax == 0 ? EPI_STORE : EPI_ACCUM);
+      rc = sweep(grid, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uin[st], Uo[st], A[st], B[st], dt, mode, s);
+      if (rc) return rc;
+    }
+  }
+  return TENOM_OK;
+}
+
+int tenom_max_wave_speed(const tenom_grid* grid, double gamma, const double* U, double* out_host, void* stream) {
+  g_err[0] = 0;
+  int rc = check_grid(grid, 1);
+  if (rc) return rc;
+  if (!U || !out_host) return fail(TENOM_EINVAL, "U and out_host must not be NULL");
+  if (grid->system == TENOM_SYS_EULER && !(gamma > 1.0 && isfinite(gamma)))
+    return fail(TENOM_EINVAL, "gamma must be finite and > 1");
+  void* buf;
+  rc = reduction_buffer(&buf);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const Dims d = dims(grid);
+  hipError_t e = hipMemsetAsync(buf, 0, 8, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+  long blocks = (d.N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_wave_speed, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, grid->ndim, grid->system, gamma,
+                     1.0 / grid->dx[0], grid->ndim > 1 ? 1.0 / grid->dx[1] : 0.0,
+                     grid->ndim > 2 ? 1.0 / grid->dx[2] : 0.0, grid->adv[0], grid->adv[1], grid->adv[2],
+                     (unsigned long long*)buf);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "wave-speed kernel launch");
+  unsigned long long bits = 0;
+  e = hipMemcpyAsync(&bits, buf, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "wave-speed readback");
+  double v;
+  memcpy(&v, &bits, 8);
+  *out_host = v;
+  return TENOM_OK;
+}
+
+int tenom_check_finite(const tenom_grid* grid, const double* U, void* stream) {
+  g_err[0] = 0;
+  int rc = check_grid(grid, 1);
+  if (rc) return rc;
+  if (!U) return fail(TENOM_EINVAL, "U must not be NULL");
+  void* buf;
+  rc = reduction_buffer(&buf);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const long M = (long)nfields(grid) * dims(grid).N;
+  unsigned int* flag = (unsigned int*)((char*)buf + 8);
+  hipError_t e = hipMemsetAsync(flag, 0, 4, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+  long blocks = (M + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)blocks), dim3(256), 0, s, U, M, flag);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "finiteness kernel launch");
+  unsigned int h = 0;
+  e = hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "finiteness readback");
+  return h ? fail(TENOM_ENONFINITE, "state holds NaN or Inf") : TENOM_OK;
+}
+
+int tenom_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return TENOM_OK;
+}
+
+int tenom_profile_read(int64_t* counts, double* total_ms, int nkinds) {
+  g_err[0] = 0;
+  if (!counts || !total_ms || nkinds < 1) return fail(TENOM_EINVAL, "bad output arrays");
+  for (int k = 0; k < nkinds; ++k) {
+    counts[k] = 0;
+    total_ms[k] = 0.0;
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  int rc = TENOM_OK;
+  for (const ProfRec& r : g_prof_recs) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && rc == TENOM_OK) rc = hip_fail(e, "profile event");
+    if (r.kind >= 0 && r.kind < nkinds) {
+      counts[r.kind] += 1;
+      total_ms[r.kind] += ms;
+    }
+    g_event_pool.push_back(r.a);
+    g_event_pool.push_back(r.b);
+  }
+  g_prof_recs.clear();
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2010_13289_amd as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tenom.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tenom_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(T.LIB_PATH):
+        T.build_library()
+    return T.lib()
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("tenom_reconstruct_faces", "tenom_flux_divergence", "tenom_rk3_step"):
+        assert name in syms
+    assert set(syms) == set(T.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert lib.tenom_version() == 10000
+
+
+def grid(**kw):
+    g = dict(ndim=3, n=[16, 16, 16], dx=[0.1, 0.1, 0.1], bc=[0, 0, 0], system=1, adv=[0, 0, 0])
+    g.update(kw)
+    return T.Grid.of(g).to_c()
+
+
+DUMMY = C.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+
+
+@pytest.mark.parametrize("kw,scheme,lim,ct,gam,code", [
+    (dict(ndim=0), 6, 1, 1e-5, 1.4, T.EINVAL),
+    (dict(ndim=4), 6, 1, 1e-5, 1.4, T.EINVAL),
+    (dict(n=[5, 16, 16]), 6, 1, 1e-5, 1.4, T.EINVAL),   # fewer than K cells
+    (dict(n=[16, 7, 16]), 8, 1, 1e-5, 1.4, T.EINVAL),
+    (dict(dx=[0.1, -1.0, 0.1]), 6, 1, 1e-5, 1.4, T.EINVAL),
+    (dict(bc=[0, 2, 0]), 6, 1, 1e-5, 1.4, T.EINVAL),
+    (dict(system=7), 6, 1, 1e-5, 1.4, T.EUNSUPPORTED),
+    ({}, 7, 1, 1e-5, 1.4, T.EUNSUPPORTED),
+    ({}, 6, 99, 1e-5, 1.4, T.EUNSUPPORTED),
+    ({}, 6, 1, -1e-5, 1.4, T.EINVAL),
+    ({}, 6, 1, float("nan"), 1.4, T.EINVAL),
+    ({}, 6, 1, 1e-5, 1.0, T.EINVAL),
+    ({}, 6, 1, 1e-5, float("inf"), T.EINVAL),
+])
+def test_argument_errors(lib, kw, scheme, lim, ct, gam, code):
+    g = grid(**kw)
+    rc = lib.tenom_reconstruct_faces(C.byref(g), scheme, lim, ct, gam, 0, DUMMY, DUMMY, None, None)
+    assert rc == code
+    assert lib.tenom_last_error().decode()
+    rc = lib.tenom_flux_divergence(C.byref(g), scheme, lim, ct, gam, DUMMY, C.c_void_p(0x2000), None)
+    assert rc == code
+
+
+def test_pointer_and_axis_errors(lib):
+    g = grid()
+    assert lib.tenom_reconstruct_faces(C.byref(g), 6, 1, 1e-5, 1.4, 0, None, DUMMY, None, None) == T.EINVAL
+    assert lib.tenom_reconstruct_faces(C.byref(g), 6, 1, 1e-5, 1.4, 3, DUMMY, DUMMY, None, None) == T.EINVAL
+    assert lib.tenom_reconstruct_faces(None, 6, 1, 1e-5, 1.4, 0, DUMMY, DUMMY, None, None) == T.EINVAL
+    assert lib.tenom_flux_divergence(C.byref(g), 6, 1, 1e-5, 1.4, DUMMY, DUMMY, None) == T.EINVAL  # alias
+
+
+def test_rk3_workspace_and_dt_errors(lib):
+    g = grid()
+    need = lib.tenom_workspace_bytes(C.byref(g), 6)
+    assert need == 3 * 5 * 16 ** 3 * 8
+    ws = C.c_void_p(0x10000)
+    assert lib.tenom_rk3_step(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, ws, need - 1, None) == T.EWORKSPACE
+    assert lib.tenom_rk3_step(C.byref(g), 6, 1, 1e-5, 1.4, 0.0, DUMMY, ws, need, None) == T.EINVAL
+    assert lib.tenom_rk3_step(C.byref(g), 6, 1, 1e-5, 1.4, float("nan"), DUMMY, ws, need, None) == T.EINVAL
+    assert lib.tenom_rk3_step(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, C.c_void_p(0x10008), need, None) == T.EINVAL
+    assert lib.tenom_rk3_step(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, None, need, None) == T.EINVAL
+    assert lib.tenom_workspace_bytes(C.byref(grid(ndim=0)), 6) == 0
+
+
+def test_strerror_and_fields(lib):
+    for code in (0, -1, -2, -3, -4, -5, -77):
+        assert lib.tenom_strerror(code)
+    assert lib.tenom_num_fields(C.byref(grid())) == 5
+    assert lib.tenom_num_fields(C.byref(grid(ndim=2))) == 4
+    assert lib.tenom_num_fields(C.byref(grid(system=0))) == 1
