@@ -145,6 +145,17 @@ __device__ __forceinline__ long cell_at(const Line& L, int jj) {
   return L.base + (long)q * L.stride;
 }
 
+// Rusanov split f+- = (f +- alpha u)/2 of one value.  alpha*u is rounded once
+// and added without contraction, so the side that vanishes mathematically
+// (e.g. f+ when f = a u with a < 0) is exactly zero instead of the rounding
+// error of alpha*u, which the smoothness indicators would classify.
+__device__ __forceinline__ void lf_split(double f, double alpha, double u, double& plus, double& minus) {
+#pragma clang fp contract(off)
+  const double au = alpha * u;
+  plus = 0.5 * (f + au);
+  minus = 0.5 * (f - au);
+}
+
 // ---------------------------------------------------------------------------
 // Scalar advection face flux: f = a u, Rusanov split with alpha = |a|.
 // ---------------------------------------------------------------------------
@@ -156,9 +167,7 @@ __device__ __forceinline__ void scalar_face(const double* __restrict__ U, const 
 #pragma unroll
   for (int m = 0; m < K; ++m) {
     const double u = U[cell_at(L, j - K / 2 + m)];
-    const double f = a * u;
-    vp[m] = 0.5 * fma(alpha, u, f);
-    vm[K - 1 - m] = 0.5 * fma(-alpha, u, f);  // mirrored for the f- side
+    lf_split(a * u, alpha, u, vp[m], vm[K - 1 - m]);  // f- side stored mirrored
   }
   bits[0] = bits[1] = 0u;
   F = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1]);
@@ -261,10 +270,7 @@ __device__ __forceinline__ void euler_face(const double* __restrict__ U, long N,
   for (int q = 0; q < NF; ++q) {
     double vp[K], vm[K];
 #pragma unroll
-    for (int m = 0; m < K; ++m) {
-      vp[m] = 0.5 * fma(alpha, W[m][q], G[m][q]);
-      vm[K - 1 - m] = 0.5 * fma(-alpha, W[m][q], G[m][q]);
-    }
+    for (int m = 0; m < K; ++m) lf_split(G[m][q], alpha, W[m][q], vp[m], vm[K - 1 - m]);
     bits[0][q] = bits[1][q] = 0u;
     fc[q] = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0][q]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1][q]);
   }
