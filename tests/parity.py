@@ -59,6 +59,24 @@ def assert_close_fields(g, o, exclude=None, rtol=RTOL, what=""):
     return worst
 
 
+def ulp_perturbed(U, seed=97):
+    """U with every value moved by -1, 0 or +1 units in the last place."""
+    rng = np.random.default_rng(seed)
+    return U * (1.0 + np.ldexp(1.0, -52) * rng.choice([-1.0, 0.0, 1.0], size=U.shape))
+
+
+def conditioning_tol(o, o_pert, scale, rtol=RTOL, factor=4.0, keep=None):
+    """Per-field tolerance for outputs whose FP64 conditioning is worse than
+    rtol: max(rtol * scale, factor * spread), where spread is how far the
+    oracle's own output moves when its input moves by one ulp (measured on
+    the kept samples).  Equals rtol * scale wherever conditioning allows."""
+    d = np.abs(np.asarray(o_pert) - np.asarray(o))
+    if keep is not None:
+        d = d[keep]
+    spread = d.max(axis=0) if d.size else np.zeros(d.shape[-1])
+    return np.maximum(rtol * scale, factor * spread), spread
+
+
 def band_faces(band):
     """[2][nf][faces...] band bits -> boolean mask over faces."""
     return np.any(band.reshape((-1,) + band.shape[2:]) != 0, axis=0)

@@ -1,0 +1,178 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times, checked on outputs the oracle computes one by one.
+
+* 3D Euler 256^3 (TGV + density jump + perturbations, TENO6-M-MP):
+  sampled faces of each axis, sampled cells of dU/dt, and sampled cells of
+  one SSP-RK3 step (the oracle evaluates each sample from its dependency
+  cone); samples whose cone meets a face in the cutoff band are excluded.
+  The step is held to 1e-12 of each field's largest magnitude.  The
+  per-call face fluxes and divergences along z are worse conditioned: the
+  normal velocity there is only the 1e-2 perturbation, so the mass and
+  energy fluxes are ~100x smaller than the characteristic terms that
+  cancel to form them, and a one-ulp change of the input moves the
+  oracle's own result by ~1e-12 of their maximum.  Those two checks use
+  max(1e-12 * scale, 4 x the oracle's one-ulp spread) per field.
+* 1D Euler N = 4096 seeded Riemann problems, TENO8-M-TVD(minmod),
+  C_T = 1e-7: every step of a run compared with the oracle on the same
+  input, and the GPU run to t_end against the exact Riemann solution.
+* 1D advection N = 200, sin + square pulse, TENO6-M-MP, CFL 0.4, to t = 2:
+  every one of the 500 steps compared on the same input.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import exact_riemann as ER
+from parity import RTOL, conditioning_tol, field_scale, require_gpu, to_dev, to_host, ulp_perturbed
+
+pytestmark = pytest.mark.gpu
+GAMMA = 1.4
+
+
+@pytest.fixture(scope="module")
+def T():
+    require_gpu()
+    import paper_2010_13289_amd as T
+    return T
+
+
+@pytest.fixture(scope="module")
+def c3():
+    U, dx = W.tgv_3d(256, gamma=GAMMA)
+    grid = dict(ndim=3, n=[256] * 3, dx=[dx] * 3, bc=[0, 0, 0], system=1)
+    return U, grid
+
+
+def _scaled_err(g, o, scale):
+    return np.abs(g - o) / scale[None, :]
+
+
+def test_c3_faces_sampled(T, orc, c3):
+    U, grid = c3
+    Ud = to_dev(U)
+    Up = ulp_perturbed(U)
+    rng = np.random.default_rng(11)
+    for axis in range(3):
+        print(f"[c3 faces] axis={axis}", flush=True)
+        Fg, flg = T.reconstruct_faces(Ud, grid, 6, T.LIM_MP, 1e-5, GAMMA, axis, return_flags=True)
+        Fg = to_host(Fg).reshape(5, -1)
+        flg = to_host(flg).reshape(10, -1)
+        idx = rng.choice(Fg.shape[1], size=1500, replace=False)
+        Fo, flo, bdo = orc.faces_points(U, grid, 6, 1, 1e-5, GAMMA, axis, idx)
+        Fp, flp, _ = orc.faces_points(Up, grid, 6, 1, 1e-5, GAMMA, axis, idx)
+        band = np.any(bdo != 0, axis=1)
+        assert band.sum() <= 2
+        keep = ~band & np.all(flp == flo, axis=1)
+        scale = field_scale(Fg)
+        tol, spread = conditioning_tol(Fo, Fp, scale, keep=keep)
+        err = np.abs(Fg[:, idx].T - Fo)[~band]
+        print(f"  max |gpu-oracle| / scale = {(err / scale).max(axis=0)}; "
+              f"oracle 1-ulp spread / scale = {spread / scale}", flush=True)
+        assert np.all(err <= tol[None, :]), (err / scale).max(axis=0)
+        assert np.array_equal(flg[:, idx].T[~band], flo[~band])
+        del Fg, flg
+
+
+def test_c3_divergence_sampled(T, orc, c3):
+    U, grid = c3
+    dg = to_host(T.flux_divergence(to_dev(U), grid, 6, T.LIM_MP, 1e-5, GAMMA)).reshape(5, -1)
+    idx = np.random.default_rng(12).choice(dg.shape[1], size=1500, replace=False)
+    do, bh = orc.dudt_points(U, grid, 6, 1, 1e-5, GAMMA, idx)
+    dp, bhp = orc.dudt_points(ulp_perturbed(U), grid, 6, 1, 1e-5, GAMMA, idx)
+    keep = bh == 0
+    assert keep.sum() >= len(idx) - 5
+    scale = field_scale(dg)
+    tol, spread = conditioning_tol(do, dp, scale, keep=keep & (bhp == 0))
+    err = np.abs(dg[:, idx].T - do)[keep]
+    print(f"  max |gpu-oracle| / scale = {(err / scale).max(axis=0)}; "
+          f"oracle 1-ulp spread / scale = {spread / scale}", flush=True)
+    assert np.all(err <= tol[None, :]), (err / scale).max(axis=0)
+
+
+def test_c3_rk3_step_sampled(T, orc, c3):
+    """The benchmark's step: dt from the wave-speed reduction at CFL 0.4,
+    one SSP-RK3 step, workspace from tenom_workspace_bytes."""
+    U, grid = c3
+    Ud = to_dev(U)
+    rate = T.max_wave_speed(Ud, grid, GAMMA)
+    assert rate == pytest.approx(orc.max_wave_speed(U, grid, GAMMA), rel=1e-13)
+    dt = 0.4 / rate
+    ws = T.Workspace(grid, 6)
+    T.rk3_step(Ud, grid, 6, T.LIM_MP, 1e-5, GAMMA, dt, workspace=ws)
+    Ug = to_host(Ud).reshape(5, -1)
+    rng = np.random.default_rng(13)
+    idx = rng.choice(Ug.shape[1], size=48, replace=False)
+    # also the cells at the density jump and at the periodic seam
+    n = 256
+    extra = [127 + n * (5 + n * 7), 128 + n * (200 + n * 3), 0 + n * (64 + n * 64), 255 + n * (3 + n * 250)]
+    idx = np.concatenate([idx, extra])
+    print(f"[c3 rk3] oracle cones for {len(idx)} cells", flush=True)
+    Uo, bh = orc.rk3_points(U, grid, 6, 1, 1e-5, GAMMA, dt, idx)
+    keep = bh == 0
+    assert keep.sum() >= len(idx) - 3
+    err = _scaled_err(Ug[:, idx].T, Uo, field_scale(Ug))[keep]
+    assert err.max() <= RTOL, err.max()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_c2_riemann_4096(T, orc, seed):
+    n = 4096
+    left, right = W.riemann_states(seed)
+    U, dx = W.riemann_problem(n, left, right, gamma=GAMMA)
+    grid = dict(ndim=1, n=[n], dx=[dx], bc=[1], system=1)
+    sl, sr = ER.wave_speeds(left, right, GAMMA)
+    t_end = min(0.2, 0.45 / max(abs(sl), abs(sr)))
+    ws = T.Workspace(grid, 8)
+    # per-step parity on identical inputs for the first 25 steps
+    Uc = U.copy()
+    for s in range(25):
+        dt = 0.4 / orc.max_wave_speed(Uc, grid, GAMMA)
+        Uo = orc.rk3_step(Uc, grid, 8, 2, 1e-7, GAMMA, dt)
+        Ud = to_dev(Uc)
+        T.rk3_step(Ud, grid, 8, T.LIM_TVD_MINMOD, 1e-7, GAMMA, dt, workspace=ws)
+        err = np.abs(to_host(Ud) - Uo) / field_scale(Uo)[:, None]
+        assert err.max() <= RTOL, (s, err.max())
+        Uc = Uo
+    # the whole run on the GPU against the exact solution
+    Ud = to_dev(U)
+    t = 0.0
+    steps = 0
+    while t < t_end - 1e-14:
+        dt = min(0.4 / T.max_wave_speed(Ud, grid, GAMMA), t_end - t)
+        T.rk3_step(Ud, grid, 8, T.LIM_TVD_MINMOD, 1e-7, GAMMA, dt, workspace=ws)
+        t += dt
+        steps += 1
+    Ug = to_host(Ud)
+    x = W.cell_centres(n, 0.0, 1.0)
+    rho, _, _ = ER.sample(left, right, (x - 0.5) / t_end, GAMMA)
+    l1 = np.mean(np.abs(Ug[0] - rho))
+    print(f"[c2 seed {seed}] {steps} steps to t={t_end:.4f}, L1(rho) = {l1:.3e}", flush=True)
+    assert l1 < 2e-3
+    assert np.all(Ug[0] > 0)
+
+
+def test_c1_advection_all_steps(T, orc):
+    n = 200
+    u, dx = W.advection_sine_pulse(n)
+    grid = dict(ndim=1, n=[n], dx=[dx], bc=[0], system=0, adv=[1.0])
+    steps = int(round(2.0 / (0.4 * dx)))
+    dt = 2.0 / steps
+    ws = T.Workspace(grid, 6)
+    Ug_run = to_dev(u)
+    uo = u.copy()
+    worst = 0.0
+    for s in range(steps):
+        nxt = orc.rk3_step(uo, grid, 6, 1, 1e-5, GAMMA, dt)
+        Ud = to_dev(uo)
+        T.rk3_step(Ud, grid, 6, T.LIM_MP, 1e-5, GAMMA, dt, workspace=ws)
+        err = np.abs(to_host(Ud) - nxt).max() / np.abs(nxt).max()
+        worst = max(worst, err)
+        assert err <= RTOL, (s, err)
+        T.rk3_step(Ug_run, grid, 6, T.LIM_MP, 1e-5, GAMMA, dt, workspace=ws)
+        uo = nxt
+    drift = np.abs(to_host(Ug_run) - uo).max()
+    print(f"[c1] {steps} steps: worst per-step error {worst:.2e}, end-to-end drift {drift:.2e}", flush=True)
+    assert drift < 1e-10
+    assert abs(to_host(Ug_run).sum() - u.sum()) < 1e-10
