@@ -32,14 +32,22 @@ __device__ __forceinline__ double minmod4(double a, double b, double c, double d
   return fmax(lo, 0.0) + fmin(hi, 0.0);
 }
 
-// 1/x from the hardware estimate plus two Newton-Raphson steps (relative
-// error at the level of the last bit for normal x).
+// 1/x from the hardware estimate (relative error ~5e-8) plus two
+// Newton-Raphson steps: equal to IEEE 1/x for normal x.
 __device__ __forceinline__ double rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
   r = fma(r, e, r);
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
+}
+
+// 1/x with one Newton-Raphson step (relative error ~2e-15).  Used only for
+// the scale-separation measure, which reaches the output through the
+// cutoff comparison alone.
+__device__ __forceinline__ double rcp1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
 // ---------------------------------------------------------------------------
@@ -71,7 +79,7 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], double C_T, uint3
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    const double s = fma(tau, rcp(beta[k] + kEps), 1.0);
+    const double s = fma(tau, rcp1(beta[k] + kEps), 1.0);
     const double s2 = s * s;
     g[k] = s2 * s2 * s2;
     sum += g[k];
@@ -157,60 +165,75 @@ __device__ __forceinline__ void lf_split(double f, double alpha, double u, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Scalar advection face flux: f = a u, Rusanov split with alpha = |a|.
+// Per-cell physics of the Euler system, in a frame rotated so that
+// component 1 is the momentum normal to the face (storage field of rotated
+// component q: fld[q]).
 // ---------------------------------------------------------------------------
-template <int K, int LIM, bool FLAGS>
-__device__ __forceinline__ void scalar_face(const double* __restrict__ U, const Line& L, int j, double a,
-                                            double C_T, double& F, uint32_t (&bits)[2]) {
-  const double alpha = fabs(a);
-  double vp[K], vm[K];
+
+// physical flux along the normal and signal speed |u_n| + c
+template <int NF>
+__device__ __forceinline__ void cell_physics(const double (&X)[NF], double gamma, double (&F)[NF], double& lam) {
+  constexpr int ND = NF - 2;
+  const double rinv = rcp(X[0]);
+  const double un = X[1] * rinv;
+  double mu = 0.0;
 #pragma unroll
-  for (int m = 0; m < K; ++m) {
-    const double u = U[cell_at(L, j - K / 2 + m)];
-    lf_split(a * u, alpha, u, vp[m], vm[K - 1 - m]);  // f- side stored mirrored
+  for (int d = 0; d < ND; ++d) mu = fma(X[1 + d], X[1 + d], mu);
+  const double p = (gamma - 1.0) * fma(-0.5 * rinv, mu, X[NF - 1]);
+  F[0] = X[1];
+  F[1] = fma(X[1], un, p);
+#pragma unroll
+  for (int t = 1; t < ND; ++t) F[1 + t] = X[1 + t] * un;
+  F[NF - 1] = (X[NF - 1] + p) * un;
+  lam = fabs(un) + sqrt(gamma * p * rinv);
+}
+
+// what the Roe average needs of one cell: sqrt(rho), velocity, enthalpy
+template <int NF>
+struct RoeIn {
+  double rs;
+  double u[NF - 2];
+  double H;
+};
+
+template <int NF>
+__device__ __forceinline__ void roe_input(const double (&X)[NF], double gamma, RoeIn<NF>& r) {
+  constexpr int ND = NF - 2;
+  const double rinv = rcp(X[0]);
+  double q2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    r.u[d] = X[1 + d] * rinv;
+    q2 = fma(r.u[d], r.u[d], q2);
   }
-  bits[0] = bits[1] = 0u;
-  F = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1]);
+  const double p = (gamma - 1.0) * fma(-0.5 * X[0], q2, X[NF - 1]);
+  r.H = (X[NF - 1] + p) * rinv;
+  r.rs = sqrt(X[0]);
 }
 
 // ---------------------------------------------------------------------------
-// Euler face flux.  NF = ndim + 2 fields, handled in a frame rotated so that
-// component 1 is the momentum normal to the face: fld[q] is the storage
-// field of rotated component q.  Characteristic fields are ordered
-// (u_n - c, entropy, shear waves in ascending axis order, u_n + c).
+// Euler face flux from a cell provider P:
+//   prov.cell(m, X, F, lam)  window cell m = 0..K-1 (cells i-K/2+1 .. i+K/2)
+//   prov.roe(s, r)           Roe input of cell i (s = 0) and i+1 (s = 1)
+// Characteristic fields are ordered (u_n - c, entropy, shear waves in
+// ascending axis order, u_n + c).
 // ---------------------------------------------------------------------------
-template <int NF, int K, int LIM, bool FLAGS>
-__device__ __forceinline__ void euler_face(const double* __restrict__ U, long N, const int (&fld)[NF],
-                                           const Line& L, int j, double gamma, double C_T, double (&Fh)[NF],
+template <int NF, int K, int LIM, bool FLAGS, class P>
+__device__ __forceinline__ void euler_face(P& prov, double gamma, double C_T, double (&Fh)[NF],
                                            uint32_t (&bits)[2][NF]) {
   constexpr int ND = NF - 2;
-  constexpr int C0 = K / 2 - 1;
   const double gm1 = gamma - 1.0;
 
-  // Roe average of cells i = j-1 and i+1 = j
+  // Roe average of cells i and i+1
   double ut[ND], Ht, ct;
   {
-    double rs[2], vel[2][ND], H[2];
+    RoeIn<NF> a, b;
+    prov.roe(0, a);
+    prov.roe(1, b);
+    const double w = rcp(a.rs + b.rs);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const long cell = cell_at(L, j - 1 + s);
-      const double rho = U[cell];
-      const double rinv = rcp(rho);
-      double q2 = 0.0;
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        vel[s][d] = U[fld[1 + d] * N + cell] * rinv;
-        q2 = fma(vel[s][d], vel[s][d], q2);
-      }
-      const double E = U[fld[NF - 1] * N + cell];
-      const double p = gm1 * fma(-0.5 * rho, q2, E);
-      H[s] = (E + p) * rinv;
-      rs[s] = sqrt(rho);
-    }
-    const double w = rcp(rs[0] + rs[1]);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) ut[d] = (rs[0] * vel[0][d] + rs[1] * vel[1][d]) * w;
-    Ht = (rs[0] * H[0] + rs[1] * H[1]) * w;
+    for (int d = 0; d < ND; ++d) ut[d] = fma(a.rs, a.u[d], b.rs * b.u[d]) * w;
+    Ht = fma(a.rs, a.H, b.rs * b.H) * w;
     double q2 = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) q2 = fma(ut[d], ut[d], q2);
@@ -237,29 +260,14 @@ __device__ __forceinline__ void euler_face(const double* __restrict__ U, long N,
     w[NF - 1] = 0.5 * (A - B);
   };
 
-  // stencil cells: physical flux, signal speed, characteristic projections
+  // stencil cells: characteristic projections of U and F, Rusanov alpha
   double W[K][NF], G[K][NF];
   double alpha = 0.0;
 #pragma unroll
   for (int m = 0; m < K; ++m) {
-    const long cell = cell_at(L, j - K / 2 + m);
-    double X[NF];
-#pragma unroll
-    for (int q = 0; q < NF; ++q) X[q] = U[fld[q] * N + cell];
-    const double rinv = rcp(X[0]);
-    const double un = X[1] * rinv;
-    double mu = 0.0;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) mu = fma(X[1 + d], X[1 + d], mu);
-    const double p = gm1 * fma(-0.5 * rinv, mu, X[NF - 1]);
-    double F[NF];
-    F[0] = X[1];
-    F[1] = fma(X[1], un, p);
-#pragma unroll
-    for (int t = 1; t < ND; ++t) F[1 + t] = X[1 + t] * un;
-    F[NF - 1] = (X[NF - 1] + p) * un;
-    const double c = sqrt(gamma * p * rinv);
-    alpha = fmax(alpha, fabs(un) + c);
+    double X[NF], F[NF], lam;
+    prov.cell(m, X, F, lam);
+    alpha = fmax(alpha, lam);
     project(X, W[m]);
     project(F, G[m]);
   }
@@ -274,7 +282,6 @@ __device__ __forceinline__ void euler_face(const double* __restrict__ U, long N,
     bits[0][q] = bits[1][q] = 0u;
     fc[q] = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0][q]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1][q]);
   }
-  (void)C0;
 
   // back to conservative variables with the right eigenvectors
   const double s = fc[0] + fc[1] + fc[NF - 1];
@@ -292,26 +299,69 @@ __device__ __forceinline__ void euler_face(const double* __restrict__ U, long N,
 }
 
 // ---------------------------------------------------------------------------
-// Dispatch on the system: NF == 1 is scalar advection, otherwise Euler.
+// Scalar advection face flux from a provider: prov.value(m) = u of window
+// cell m.  f = a u, Rusanov split with alpha = |a|.
 // ---------------------------------------------------------------------------
+template <int K, int LIM, bool FLAGS, class P>
+__device__ __forceinline__ void scalar_face(P& prov, double a, double C_T, double& F, uint32_t (&bits)[2]) {
+  const double alpha = fabs(a);
+  double vp[K], vm[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    const double u = prov.value(m);
+    lf_split(a * u, alpha, u, vp[m], vm[K - 1 - m]);  // f- side stored mirrored
+  }
+  bits[0] = bits[1] = 0u;
+  F = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1]);
+}
+
 struct FaceParams {
   double gamma;
   double C_T;
   double adv;  // advection speed along the axis (scalar system)
 };
 
-template <int NF, int K, int LIM, bool FLAGS>
-__device__ __forceinline__ void face_flux(const double* __restrict__ U, long N, const int (&fld)[NF],
-                                          const Line& L, int j, const FaceParams& fp, double (&F)[NF],
-                                          uint32_t (&bits)[2][NF]) {
+// Dispatch on the system: NF == 1 is scalar advection, otherwise Euler.
+template <int NF, int K, int LIM, bool FLAGS, class P>
+__device__ __forceinline__ void face_flux(P& prov, const FaceParams& fp, double (&F)[NF], uint32_t (&bits)[2][NF]) {
   if constexpr (NF == 1) {
     uint32_t b[2];
-    scalar_face<K, LIM, FLAGS>(U, L, j, fp.adv, fp.C_T, F[0], b);
+    scalar_face<K, LIM, FLAGS>(prov, fp.adv, fp.C_T, F[0], b);
     bits[0][0] = b[0];
     bits[1][0] = b[1];
   } else {
-    euler_face<NF, K, LIM, FLAGS>(U, N, fld, L, j, fp.gamma, fp.C_T, F, bits);
+    euler_face<NF, K, LIM, FLAGS>(prov, fp.gamma, fp.C_T, F, bits);
   }
 }
+
+// ---------------------------------------------------------------------------
+// Cell providers
+// ---------------------------------------------------------------------------
+
+// straight from global memory (face j of a line)
+template <int NF, int K>
+struct GlobalCells {
+  const double* __restrict__ U;
+  long N;
+  const int* fld;
+  Line L;
+  int j;
+  double gamma;
+  __device__ __forceinline__ void load(int pos, double (&X)[NF]) const {
+    const long cell = cell_at(L, pos);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) X[q] = U[fld[q] * N + cell];
+  }
+  __device__ __forceinline__ void cell(int m, double (&X)[NF], double (&F)[NF], double& lam) const {
+    load(j - K / 2 + m, X);
+    cell_physics<NF>(X, gamma, F, lam);
+  }
+  __device__ __forceinline__ void roe(int s, RoeIn<NF>& r) const {
+    double X[NF];
+    load(j - 1 + s, X);
+    roe_input<NF>(X, gamma, r);
+  }
+  __device__ __forceinline__ double value(int m) const { return U[cell_at(L, j - K / 2 + m)]; }
+};
 
 }  // namespace tenom

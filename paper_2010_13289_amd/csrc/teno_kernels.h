@@ -4,13 +4,17 @@
 //                  (and optionally the smoothness flags).  The unit the
 //                  reconstruct_faces call exposes.
 //  k_sweep_row     sweep along x (unit stride).  A 256-thread workgroup owns
-//                  one row segment: each thread computes one face flux into
-//                  LDS, then each thread forms one cell's divergence and
-//                  applies the epilogue.  A periodic row of <= 256 cells is
-//                  one segment, so every face is computed exactly once.
+//                  one row segment: the segment's cells are staged in LDS
+//                  with their flux, signal speed and Roe inputs, each thread
+//                  computes one face flux, the fluxes go back to LDS, then
+//                  each thread forms one cell's divergence and applies the
+//                  epilogue.  A periodic row of <= 256 cells is one segment,
+//                  so every face and every cell is computed exactly once.
 //  k_sweep_march   sweep along y or z (strided).  Each lane owns one x
 //                  column (coalesced 512-byte rows per wave) and marches
-//                  along the axis over a segment of cells, carrying the
+//                  along the axis over a segment of cells, keeping the face's
+//                  K cells in an LDS ring (one new cell fetched per face,
+//                  while the previous face computes) and carrying the
 //                  previous face flux in registers; M cells cost M+1 faces
 //                  (M faces for a whole periodic line).
 //
@@ -91,60 +95,169 @@ __global__ __launch_bounds__(256) void k_faces(const double* __restrict__ U, dou
   int fld[NF];
 #pragma unroll
   for (int q = 0; q < NF; ++q) fld[q] = fall[q];
+  GlobalCells<NF, K> prov{U, N, fld, L, j, fp.gamma};
   double F[NF];
   uint32_t bits[2][NF];
   if (flags) {
-    face_flux<NF, K, LIM, true>(U, N, fld, L, j, fp, F, bits);
+    face_flux<NF, K, LIM, true>(prov, fp, F, bits);
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
       flags[(long)q * nfaces + t] = (uint8_t)bits[0][q];
       flags[(long)(NF + q) * nfaces + t] = (uint8_t)bits[1][q];
     }
   } else {
-    face_flux<NF, K, LIM, false>(U, N, fld, L, j, fp, F, bits);
+    face_flux<NF, K, LIM, false>(prov, fp, F, bits);
   }
 #pragma unroll
   for (int q = 0; q < NF; ++q) Fhat[(long)fld[q] * nfaces + t] = F[q];
 }
 
 // ---------------------------------------------------------------------------
+// Row sweep.  Cells of the segment (plus K-1 halo cells) are staged once in
+// LDS together with their physical flux, signal speed and Roe inputs, so a
+// face reads its K cells instead of recomputing them.
+// ---------------------------------------------------------------------------
+template <int NF>
+struct RowStage {
+  static constexpr int NE = (NF == 1) ? 1 : 3 * NF + 1;  // U, F, lambda, Roe input
+};
+
+template <int NF, int K>
+struct StagedCells {
+  const double* s;  // LDS: [NE][NC]
+  int nc;           // row pitch of the staging array
+  int c0;           // staging index of window cell 0
+  __device__ __forceinline__ double at(int e, int c) const { return s[e * nc + c]; }
+  __device__ __forceinline__ void cell(int m, double (&X)[NF], double (&F)[NF], double& lam) const {
+    const int c = c0 + m;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      X[q] = at(q, c);
+      F[q] = at(NF + q, c);
+    }
+    lam = at(2 * NF, c);
+  }
+  __device__ __forceinline__ void roe(int sd, RoeIn<NF>& r) const {
+    const int c = c0 + K / 2 - 1 + sd;
+    r.rs = at(2 * NF + 1, c);
+#pragma unroll
+    for (int d = 0; d < NF - 2; ++d) r.u[d] = at(2 * NF + 2 + d, c);
+    r.H = at(3 * NF, c);
+  }
+  __device__ __forceinline__ double value(int m) const { return at(0, c0 + m); }
+};
+
 template <int NF, int K, int LIM>
 __global__ __launch_bounds__(256) void k_sweep_row(SweepParams<NF> p) {
-  __shared__ double Fs[NF][257];
+  constexpr int NC = 256 + K - 1;  // staged cells per segment
+  constexpr int NE = RowStage<NF>::NE;
+  __shared__ double stage[NE * NC];
   const int s = blockIdx.x % p.nseg;
   const long row = blockIdx.x / p.nseg;  // y + ny * z
   const int c_begin = s * p.seg;
   const int ncell = min(p.seg, p.n - c_begin);
   const bool wrap = (p.bc == 0) && (p.seg >= p.n);  // whole periodic row
   const int nface = wrap ? p.n : ncell + 1;
+  const int nstage = nface + K - 1;
   const long N = (long)p.nx * p.ny * p.nz;
   const Line L{row * p.nx, 1, p.n, p.bc};
   const int t = threadIdx.x;
-  if (t < nface) {
-    double F[NF];
-    uint32_t bits[2][NF];
-    face_flux<NF, K, LIM, false>(p.U, N, p.fld, L, c_begin + t, p.fp, F, bits);
+
+  // stage cells c_begin - K/2 .. c_begin + nface + K/2 - 2
+  for (int c = t; c < nstage; c += 256) {
+    const long cell = cell_at(L, c_begin - K / 2 + c);
+    double X[NF];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) Fs[q][t] = F[q];
+    for (int q = 0; q < NF; ++q) X[q] = p.U[p.fld[q] * N + cell];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) stage[q * NC + c] = X[q];
+    if constexpr (NF > 1) {
+      double F[NF], lam;
+      RoeIn<NF> r;
+      cell_physics<NF>(X, p.fp.gamma, F, lam);
+      roe_input<NF>(X, p.fp.gamma, r);
+#pragma unroll
+      for (int q = 0; q < NF; ++q) stage[(NF + q) * NC + c] = F[q];
+      stage[(2 * NF) * NC + c] = lam;
+      stage[(2 * NF + 1) * NC + c] = r.rs;
+#pragma unroll
+      for (int d = 0; d < NF - 2; ++d) stage[(2 * NF + 2 + d) * NC + c] = r.u[d];
+      stage[(3 * NF) * NC + c] = r.H;
+    }
+  }
+  __syncthreads();
+
+  double F[NF];
+  if (t < nface) {
+    StagedCells<NF, K> prov{stage, NC, t};
+    uint32_t bits[2][NF];
+    face_flux<NF, K, LIM, false>(prov, p.fp, F, bits);
+  }
+  __syncthreads();  // every face has read the staged cells
+  double* Fs = stage;  // reuse: [NF][257]
+  if (t < nface) {
+#pragma unroll
+    for (int q = 0; q < NF; ++q) Fs[q * 257 + t] = F[q];
   }
   __syncthreads();
   if (t < ncell) {
     const int r = (wrap && t == p.n - 1) ? 0 : t + 1;
     double div[NF];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) div[q] = (Fs[q][t] - Fs[q][r]) * p.inv_dx;
+    for (int q = 0; q < NF; ++q) div[q] = (Fs[q * 257 + t] - Fs[q * 257 + r]) * p.inv_dx;
     epilogue<NF>(p, N, L.base + c_begin + t, div);
   }
 }
 
 // ---------------------------------------------------------------------------
-// blockDim = (64, 4): x = lane, y = line within the block; axis = 1 or 2
+// March sweep (axis 1 or 2).  blockDim = (64, LINES): x = lane, y = line.
+// Each lane keeps the K cell states of its current face in an LDS ring
+// (slot of window cell m: (slot0 + m) mod K) and fetches the one new cell of
+// the next face while the current face is computed.
+// ---------------------------------------------------------------------------
+template <int NF, int K>
+struct RingCells {
+  const double* ring;  // LDS: [K][NF][T] with T threads per block
+  int T, tid, slot0;
+  double gamma;
+  __device__ __forceinline__ void load(int m, double (&X)[NF]) const {
+    int sl = slot0 + m;
+    sl = sl >= K ? sl - K : sl;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) X[q] = ring[(sl * NF + q) * T + tid];
+  }
+  __device__ __forceinline__ void cell(int m, double (&X)[NF], double (&F)[NF], double& lam) const {
+    load(m, X);
+    cell_physics<NF>(X, gamma, F, lam);
+  }
+  __device__ __forceinline__ void roe(int s, RoeIn<NF>& r) const {
+    double X[NF];
+    load(K / 2 - 1 + s, X);
+    roe_input<NF>(X, gamma, r);
+  }
+  __device__ __forceinline__ double value(int m) const {
+    int sl = slot0 + m;
+    sl = sl >= K ? sl - K : sl;
+    return ring[sl * NF * T + tid];
+  }
+};
+
+template <int NF, int K>
+struct MarchShape {
+  // lines per block: 4, or 2 when the ring of 4 lines would exceed 64 KiB
+  static constexpr int LINES = (K * NF * 8 * 64 * 4 <= 65536) ? 4 : 2;
+};
+
 template <int NF, int K, int LIM>
-__global__ __launch_bounds__(256) void k_sweep_march(SweepParams<NF> p, int axis) {
+__global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march(SweepParams<NF> p, int axis) {
+  constexpr int LINES = MarchShape<NF, K>::LINES;
+  constexpr int T = 64 * LINES;
+  __shared__ double ring[K * NF * T];
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int n_other = (axis == 1) ? p.nz : p.ny;
-  const int o = blockIdx.y * 4 + threadIdx.y;
-  if (x >= p.nx || o >= n_other) return;
+  const int o = blockIdx.y * LINES + threadIdx.y;
+  if (x >= p.nx || o >= n_other) return;  // no block-wide barrier follows
+  const int tid = threadIdx.y * 64 + threadIdx.x;
   const int s = blockIdx.z;
   const long N = (long)p.nx * p.ny * p.nz;
   Line L;
@@ -155,16 +268,42 @@ __global__ __launch_bounds__(256) void k_sweep_march(SweepParams<NF> p, int axis
   const int c_begin = s * p.seg;
   const int ncell = min(p.seg, p.n - c_begin);
   const bool wrap = (p.bc == 0) && (p.seg >= p.n);
+  const int nface = wrap ? ncell : ncell + 1;  // faces computed (not reused)
+
+  auto fetch = [&](int pos, double (&X)[NF]) {
+    const long cell = cell_at(L, pos);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) X[q] = p.U[p.fld[q] * N + cell];
+  };
+  // window of the first face
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    double X[NF];
+    fetch(c_begin - K / 2 + m, X);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) ring[(m * NF + q) * T + tid] = X[q];
+  }
+  int slot0 = 0;
   double Fprev[NF], Ffirst[NF];
   for (int t = 0; t <= ncell; ++t) {
     double F[NF];
-    if (wrap && t == ncell) {
+    if (t == nface) {  // periodic line: face n is face 0
 #pragma unroll
       for (int q = 0; q < NF; ++q) F[q] = Ffirst[q];
     } else {
+      const int j = c_begin + t;
+      const bool more = (t + 1 < nface);
+      double nxt[NF];
+      if (more) fetch(j + K / 2, nxt);  // the new cell of face j + 1
+      RingCells<NF, K> prov{ring, T, tid, slot0, p.fp.gamma};
       uint32_t bits[2][NF];
-      face_flux<NF, K, LIM, false>(p.U, N, p.fld, L, c_begin + t, p.fp, F, bits);
-      if (wrap && t == 0) {
+      face_flux<NF, K, LIM, false>(prov, p.fp, F, bits);
+      if (more) {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) ring[(slot0 * NF + q) * T + tid] = nxt[q];
+        slot0 = (slot0 + 1 == K) ? 0 : slot0 + 1;
+      }
+      if (t == 0) {
 #pragma unroll
         for (int q = 0; q < NF; ++q) Ffirst[q] = F[q];
       }
@@ -249,8 +388,9 @@ hipError_t launch_sweep(const SweepLaunch& a) {
     p.seg = a.seg >= p.n ? p.n : a.seg;
     p.nseg = (p.n + p.seg - 1) / p.seg;
     const int n_other = (a.axis == 1) ? a.nz : a.ny;
-    dim3 grid((a.nx + 63) / 64, (n_other + 3) / 4, p.nseg);
-    hipLaunchKernelGGL((k_sweep_march<NF, K, LIM>), grid, dim3(64, 4), 0, a.stream, p, a.axis);
+    constexpr int LINES = MarchShape<NF, K>::LINES;
+    dim3 grid((a.nx + 63) / 64, (n_other + LINES - 1) / LINES, p.nseg);
+    hipLaunchKernelGGL((k_sweep_march<NF, K, LIM>), grid, dim3(64, LINES), 0, a.stream, p, a.axis);
   }
   return hipGetLastError();
 }
