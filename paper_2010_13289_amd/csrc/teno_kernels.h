@@ -13,10 +13,11 @@
 //  k_sweep_march   sweep along y or z (strided).  Each lane owns one x
 //                  column (coalesced 512-byte rows per wave) and marches
 //                  along the axis over a segment of cells, keeping the face's
-//                  K cells in an LDS ring (one new cell fetched per face,
-//                  while the previous face computes) and carrying the
-//                  previous face flux in registers; M cells cost M+1 faces
-//                  (M faces for a whole periodic line).
+//                  K cells in an LDS ring and carrying the previous face
+//                  flux in registers.  The next face's new cell and the
+//                  epilogue operands of the cell being closed are loaded
+//                  before the face is computed, so their latency hides
+//                  behind it.  M cells cost M+1 faces.
 //
 // Sweep epilogues (divergence -dF/dx of the axis, then):
 //  STORE  R = div                      ACCUM  R += div
@@ -48,21 +49,47 @@ struct SweepParams {
   FaceParams fp;
 };
 
+// Operands the epilogue reads: R (ACCUM, RK), U_s and U^n (RK).  Loaded by
+// epi_load so that a caller can issue them early and hide their latency.
 template <int NF>
-__device__ __forceinline__ void epilogue(const SweepParams<NF>& p, long N, long cell, const double (&div)[NF]) {
+struct EpiIn {
+  double r[NF], us[NF], u0[NF];
+};
+
+template <int NF>
+__device__ __forceinline__ void epi_load(const SweepParams<NF>& p, long N, long cell, EpiIn<NF>& in) {
+#pragma unroll
+  for (int q = 0; q < NF; ++q) {
+    const long o = (long)p.fld[q] * N + cell;
+    in.r[q] = (p.mode == EPI_ACCUM || p.mode == EPI_RK) ? p.R[o] : 0.0;
+    in.us[q] = (p.mode >= EPI_RK) ? p.Us[o] : 0.0;
+    in.u0[q] = (p.mode >= EPI_RK && p.a != 0.0) ? p.U0[o] : 0.0;
+  }
+}
+
+template <int NF>
+__device__ __forceinline__ void epi_store(const SweepParams<NF>& p, long N, long cell, const double (&div)[NF],
+                                          const EpiIn<NF>& in) {
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
     const long o = (long)p.fld[q] * N + cell;
     if (p.mode == EPI_STORE) {
       p.R[o] = div[q];
     } else if (p.mode == EPI_ACCUM) {
-      p.R[o] = p.R[o] + div[q];
+      p.R[o] = in.r[q] + div[q];
     } else {
-      const double rhs = (p.mode == EPI_RK) ? p.R[o] + div[q] : div[q];
-      const double us = fma(p.dt, rhs, p.Us[o]);
-      p.Uout[o] = (p.a != 0.0) ? fma(p.a, p.U0[o], p.b * us) : p.b * us;
+      const double rhs = (p.mode == EPI_RK) ? in.r[q] + div[q] : div[q];
+      const double us = fma(p.dt, rhs, in.us[q]);
+      p.Uout[o] = (p.a != 0.0) ? fma(p.a, in.u0[q], p.b * us) : p.b * us;
     }
   }
+}
+
+template <int NF>
+__device__ __forceinline__ void epilogue(const SweepParams<NF>& p, long N, long cell, const double (&div)[NF]) {
+  EpiIn<NF> in;
+  epi_load<NF>(p, N, cell, in);
+  epi_store<NF>(p, N, cell, div, in);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,8 +294,8 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
     L = Line{x + (long)p.nx * o, (long)p.nx * p.ny, p.nz, p.bc};
   const int c_begin = s * p.seg;
   const int ncell = min(p.seg, p.n - c_begin);
-  const bool wrap = (p.bc == 0) && (p.seg >= p.n);
-  const int nface = wrap ? ncell : ncell + 1;  // faces computed (not reused)
+  // faces c_begin .. c_begin + ncell; on a whole periodic line face n reads
+  // the same wrapped cells as face 0, so its flux is recomputed bit for bit
 
   auto fetch = [&](int pos, double (&X)[NF]) {
     const long cell = cell_at(L, pos);
@@ -284,35 +311,31 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
     for (int q = 0; q < NF; ++q) ring[(m * NF + q) * T + tid] = X[q];
   }
   int slot0 = 0;
-  double Fprev[NF], Ffirst[NF];
+  double Fprev[NF];
   for (int t = 0; t <= ncell; ++t) {
+    const int j = c_begin + t;
+    const bool more = (t < ncell);
+    double nxt[NF];
+    if (more) fetch(j + K / 2, nxt);  // the new cell of face j + 1
+    const long ecell = L.base + (long)(j - 1) * L.stride;  // cell closed by face j
+    EpiIn<NF> ein;
+    if (t > 0) epi_load<NF>(p, N, ecell, ein);
     double F[NF];
-    if (t == nface) {  // periodic line: face n is face 0
-#pragma unroll
-      for (int q = 0; q < NF; ++q) F[q] = Ffirst[q];
-    } else {
-      const int j = c_begin + t;
-      const bool more = (t + 1 < nface);
-      double nxt[NF];
-      if (more) fetch(j + K / 2, nxt);  // the new cell of face j + 1
+    {
       RingCells<NF, K> prov{ring, T, tid, slot0, p.fp.gamma};
       uint32_t bits[2][NF];
       face_flux<NF, K, LIM, false>(prov, p.fp, F, bits);
-      if (more) {
+    }
+    if (more) {
 #pragma unroll
-        for (int q = 0; q < NF; ++q) ring[(slot0 * NF + q) * T + tid] = nxt[q];
-        slot0 = (slot0 + 1 == K) ? 0 : slot0 + 1;
-      }
-      if (t == 0) {
-#pragma unroll
-        for (int q = 0; q < NF; ++q) Ffirst[q] = F[q];
-      }
+      for (int q = 0; q < NF; ++q) ring[(slot0 * NF + q) * T + tid] = nxt[q];
+      slot0 = (slot0 + 1 == K) ? 0 : slot0 + 1;
     }
     if (t > 0) {
       double div[NF];
 #pragma unroll
       for (int q = 0; q < NF; ++q) div[q] = (Fprev[q] - F[q]) * p.inv_dx;
-      epilogue<NF>(p, N, L.base + (long)(c_begin + t - 1) * L.stride, div);
+      epi_store<NF>(p, N, ecell, div, ein);
     }
 #pragma unroll
     for (int q = 0; q < NF; ++q) Fprev[q] = F[q];
