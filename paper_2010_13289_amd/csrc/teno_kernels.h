@@ -22,6 +22,8 @@
 // Sweep epilogues (divergence -dF/dx of the axis, then):
 //  STORE  R = div                      ACCUM  R += div
 //  RK     Uout = a U0 + b (Us + dt (R + div))      RK1   Uout = a U0 + b (Us + dt div)
+// where Us is the stage state the stencils read (p.U); the kernels take it
+// from their LDS copy of the cell instead of reading HBM again.
 #pragma once
 
 #include "teno_device.h"
@@ -35,7 +37,6 @@ struct SweepParams {
   const double* U;   // state the stencils read
   double* R;         // divergence accumulator (STORE/ACCUM write, RK reads)
   const double* U0;  // RK: U^n
-  const double* Us;  // RK: stage state
   double* Uout;      // RK: output state
   double a, b, dt;   // RK coefficients
   int mode;
@@ -49,11 +50,11 @@ struct SweepParams {
   FaceParams fp;
 };
 
-// Operands the epilogue reads: R (ACCUM, RK), U_s and U^n (RK).  Loaded by
-// epi_load so that a caller can issue them early and hide their latency.
+// Operands the epilogue reads from HBM: R (ACCUM, RK) and U^n (RK with
+// a != 0).  Loaded by epi_load so that a caller can issue them early.
 template <int NF>
 struct EpiIn {
-  double r[NF], us[NF], u0[NF];
+  double r[NF], u0[NF];
 };
 
 template <int NF>
@@ -62,14 +63,14 @@ __device__ __forceinline__ void epi_load(const SweepParams<NF>& p, long N, long 
   for (int q = 0; q < NF; ++q) {
     const long o = (long)p.fld[q] * N + cell;
     in.r[q] = (p.mode == EPI_ACCUM || p.mode == EPI_RK) ? p.R[o] : 0.0;
-    in.us[q] = (p.mode >= EPI_RK) ? p.Us[o] : 0.0;
     in.u0[q] = (p.mode >= EPI_RK && p.a != 0.0) ? p.U0[o] : 0.0;
   }
 }
 
+// us: the cell's stage state (rotated components), only used by RK modes
 template <int NF>
 __device__ __forceinline__ void epi_store(const SweepParams<NF>& p, long N, long cell, const double (&div)[NF],
-                                          const EpiIn<NF>& in) {
+                                          const EpiIn<NF>& in, const double (&us)[NF]) {
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
     const long o = (long)p.fld[q] * N + cell;
@@ -79,17 +80,10 @@ __device__ __forceinline__ void epi_store(const SweepParams<NF>& p, long N, long
       p.R[o] = in.r[q] + div[q];
     } else {
       const double rhs = (p.mode == EPI_RK) ? in.r[q] + div[q] : div[q];
-      const double us = fma(p.dt, rhs, in.us[q]);
-      p.Uout[o] = (p.a != 0.0) ? fma(p.a, in.u0[q], p.b * us) : p.b * us;
+      const double v = fma(p.dt, rhs, us[q]);
+      p.Uout[o] = (p.a != 0.0) ? fma(p.a, in.u0[q], p.b * v) : p.b * v;
     }
   }
-}
-
-template <int NF>
-__device__ __forceinline__ void epilogue(const SweepParams<NF>& p, long N, long cell, const double (&div)[NF]) {
-  EpiIn<NF> in;
-  epi_load<NF>(p, N, cell, in);
-  epi_store<NF>(p, N, cell, div, in);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,6 +214,13 @@ __global__ __launch_bounds__(256) void k_sweep_row(SweepParams<NF> p) {
     uint32_t bits[2][NF];
     face_flux<NF, K, LIM, false>(prov, p.fp, F, bits);
   }
+  // stage state of this thread's cell (staged at t + K/2), copied before the
+  // staging array is reused
+  double us[NF];
+  if (t < ncell) {
+#pragma unroll
+    for (int q = 0; q < NF; ++q) us[q] = stage[q * NC + t + K / 2];
+  }
   __syncthreads();  // every face has read the staged cells
   double* Fs = stage;  // reuse: [NF][257]
   if (t < nface) {
@@ -228,11 +229,14 @@ __global__ __launch_bounds__(256) void k_sweep_row(SweepParams<NF> p) {
   }
   __syncthreads();
   if (t < ncell) {
+    const long cell = L.base + c_begin + t;
+    EpiIn<NF> ein;
+    epi_load<NF>(p, N, cell, ein);
     const int r = (wrap && t == p.n - 1) ? 0 : t + 1;
     double div[NF];
 #pragma unroll
     for (int q = 0; q < NF; ++q) div[q] = (Fs[q * 257 + t] - Fs[q * 257 + r]) * p.inv_dx;
-    epilogue<NF>(p, N, L.base + c_begin + t, div);
+    epi_store<NF>(p, N, cell, div, ein, us);
   }
 }
 
@@ -319,10 +323,12 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
     if (more) fetch(j + K / 2, nxt);  // the new cell of face j + 1
     const long ecell = L.base + (long)(j - 1) * L.stride;  // cell closed by face j
     EpiIn<NF> ein;
+    double us[NF];
     if (t > 0) epi_load<NF>(p, N, ecell, ein);
     double F[NF];
     {
       RingCells<NF, K> prov{ring, T, tid, slot0, p.fp.gamma};
+      prov.load(K / 2 - 1, us);  // cell j - 1 is window cell K/2 - 1 of face j
       uint32_t bits[2][NF];
       face_flux<NF, K, LIM, false>(prov, p.fp, F, bits);
     }
@@ -335,7 +341,7 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
       double div[NF];
 #pragma unroll
       for (int q = 0; q < NF; ++q) div[q] = (Fprev[q] - F[q]) * p.inv_dx;
-      epi_store<NF>(p, N, ecell, div, ein);
+      epi_store<NF>(p, N, ecell, div, ein, us);
     }
 #pragma unroll
     for (int q = 0; q < NF; ++q) Fprev[q] = F[q];
@@ -360,7 +366,6 @@ struct SweepLaunch {
   const double* U;
   double* R;
   const double* U0;
-  const double* Us;
   double* Uout;
   double a, b, dt;
   int mode;
@@ -387,7 +392,6 @@ hipError_t launch_sweep(const SweepLaunch& a) {
   p.U = a.U;
   p.R = a.R;
   p.U0 = a.U0;
-  p.Us = a.Us;
   p.Uout = a.Uout;
   p.a = a.a;
   p.b = a.b;

@@ -189,10 +189,10 @@ int march_segment(int n, int nx, int n_other) {
   return (int)seg;
 }
 
-// Launch one sweep of `axis` with the given epilogue.
+// Launch one sweep of `axis` with the given epilogue.  In the RK modes the
+// stage state U_s of the update is U, the state the stencils read.
 int sweep(const tenom_grid* g, int K, int limiter, double C_T, double gamma, int axis, const double* U, double* R,
-          const double* U0, const double* Us, double* Uout, double a, double b, double dt, int mode,
-          hipStream_t stream) {
+          const double* U0, double* Uout, double a, double b, double dt, int mode, hipStream_t stream) {
   FacesFn ff;
   SweepFn sf;
   const int nf = nfields(g);
@@ -203,7 +203,6 @@ int sweep(const tenom_grid* g, int K, int limiter, double C_T, double gamma, int
   L.U = U;
   L.R = R;
   L.U0 = U0;
-  L.Us = Us;
   L.Uout = Uout;
   L.a = a;
   L.b = b;
@@ -367,7 +366,7 @@ int tenom_flux_divergence(const tenom_grid* grid, int scheme, int limiter, doubl
   if ((const void*)U == (const void*)dUdt) return fail(TENOM_EINVAL, "dUdt must not alias U");
   hipStream_t s = (hipStream_t)stream;
   for (int ax = 0; ax < grid->ndim; ++ax) {
-    rc = sweep(grid, scheme, limiter, C_T, gamma, ax, U, dUdt, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0,
+    rc = sweep(grid, scheme, limiter, C_T, gamma, ax, U, dUdt, nullptr, nullptr, 0.0, 0.0, 0.0,
                ax == 0 ? EPI_STORE : EPI_ACCUM, s);
     if (rc) return rc;
   }
@@ -408,7 +407,7 @@ int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, 
     for (int ax = 0; ax < nd; ++ax) {
       const bool last = (ax == nd - 1);
       int mode = last ? (nd == 1 ? EPI_RK1 : EPI_RK) : (ax == 0 ? EPI_STORE : EPI_ACCUM);
-      rc = sweep(grid, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uin[st], Uo[st], A[st], B[st], dt, mode, s);
+      rc = sweep(grid, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uo[st], A[st], B[st], dt, mode, s);
       if (rc) return rc;
     }
   }
