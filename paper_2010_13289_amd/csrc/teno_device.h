@@ -15,8 +15,12 @@
 
 namespace tenom {
 
-// Eq. measureTENO: gamma_k = (C + tau_K / (beta_k + eps))^q, C = 1, q = 6
+// Eq. measureTENO: gamma_k = (C + tau_K / (beta_k + eps))^q, C = 1, q = 6.
+// The reconstruction runs on twice the split fluxes (see lf_split2), which
+// scales beta and tau by 4; eps is scaled by the same exact factor, so every
+// rounding step is the same as on the halved values.
 constexpr double kEps = 1e-40;
+constexpr double kEps2x = 4.0 * kEps;
 
 // Limiter identifiers of the C ABI (values of TENOM_LIM_*).
 enum : int { LIM_MP = 1, LIM_TVD_MINMOD = 2, LIM_TVD5 = 3 };
@@ -54,6 +58,9 @@ __device__ __forceinline__ double rcp1(double x) {
 // One TENO-M reconstruction at x_{i+1/2} from v[0..K-1] = f_{i-K/2+1..i+K/2}
 // (Secs. 2.2-3.3).  Computed relative to v_i, in differences of adjacent
 // values.  `bits` receives delta_k (1 = smooth) in bit k when FLAGS.
+// The inputs are twice the split fluxes (lf_split2) and so is the result:
+// every step is homogeneous, with eps scaled to match, so the result is
+// exactly twice the reconstruction of the halved values.
 // ---------------------------------------------------------------------------
 template <int K, int LIM, bool FLAGS>
 __device__ __forceinline__ double teno_m(const double (&v)[K], double C_T, uint32_t& bits) {
@@ -79,7 +86,7 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], double C_T, uint3
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    const double s = fma(tau, rcp1(beta[k] + kEps), 1.0);
+    const double s = fma(tau, rcp1(beta[k] + kEps2x), 1.0);
     const double s2 = s * s;
     g[k] = s2 * s2 * s2;
     sum += g[k];
@@ -153,15 +160,17 @@ __device__ __forceinline__ long cell_at(const Line& L, int jj) {
   return L.base + (long)q * L.stride;
 }
 
-// Rusanov split f+- = (f +- alpha u)/2 of one value.  alpha*u is rounded once
-// and added without contraction, so the side that vanishes mathematically
-// (e.g. f+ when f = a u with a < 0) is exactly zero instead of the rounding
-// error of alpha*u, which the smoothness indicators would classify.
-__device__ __forceinline__ void lf_split(double f, double alpha, double u, double& plus, double& minus) {
+// Rusanov split f+- = (f +- alpha u)/2 of one value, returned doubled
+// (f +- alpha u): the halving is applied once to the reconstructed sum.
+// alpha*u is rounded once and added without contraction, so the side that
+// vanishes mathematically (e.g. f+ when f = a u with a < 0) is exactly zero
+// instead of the rounding error of alpha*u, which the smoothness indicators
+// would classify.
+__device__ __forceinline__ void lf_split2(double f, double alpha, double u, double& plus2, double& minus2) {
 #pragma clang fp contract(off)
   const double au = alpha * u;
-  plus = 0.5 * (f + au);
-  minus = 0.5 * (f - au);
+  plus2 = f + au;
+  minus2 = f - au;
 }
 
 // ---------------------------------------------------------------------------
@@ -278,9 +287,9 @@ __device__ __forceinline__ void euler_face(P& prov, double gamma, double C_T, do
   for (int q = 0; q < NF; ++q) {
     double vp[K], vm[K];
 #pragma unroll
-    for (int m = 0; m < K; ++m) lf_split(G[m][q], alpha, W[m][q], vp[m], vm[K - 1 - m]);
+    for (int m = 0; m < K; ++m) lf_split2(G[m][q], alpha, W[m][q], vp[m], vm[K - 1 - m]);
     bits[0][q] = bits[1][q] = 0u;
-    fc[q] = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0][q]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1][q]);
+    fc[q] = 0.5 * (teno_m<K, LIM, FLAGS>(vp, C_T, bits[0][q]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1][q]));
   }
 
   // back to conservative variables with the right eigenvectors
@@ -309,10 +318,10 @@ __device__ __forceinline__ void scalar_face(P& prov, double a, double C_T, doubl
 #pragma unroll
   for (int m = 0; m < K; ++m) {
     const double u = prov.value(m);
-    lf_split(a * u, alpha, u, vp[m], vm[K - 1 - m]);  // f- side stored mirrored
+    lf_split2(a * u, alpha, u, vp[m], vm[K - 1 - m]);  // f- side stored mirrored
   }
   bits[0] = bits[1] = 0u;
-  F = teno_m<K, LIM, FLAGS>(vp, C_T, bits[0]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1]);
+  F = 0.5 * (teno_m<K, LIM, FLAGS>(vp, C_T, bits[0]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1]));
 }
 
 struct FaceParams {
