@@ -55,6 +55,27 @@ FLOPS_PER_FACE_VECTOR = 2449
 # every stage, U^n also read in stages 2 and 3 (5 fields x 8 bytes each).
 BYTES_PER_CELL_STEP = 320
 
+# HBM bytes per launch of each sweep kind at 256^3, averaged over the three
+# stages, from two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE scaled
+# by 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB device copy reads
+# as).  They describe the kernels built from the sources whose digest is
+# TRAFFIC_SOURCE_DIGEST and are reported as null for any other build.
+TRAFFIC_SOURCE_DIGEST = "dac703a37bf04cb3cea84ee29149123ff9da5a6314c1926f65f68df941227ea7"
+MEASURED_TRAFFIC = {"sweep_x": 1.3425e9, "sweep_y": 2.0765e9, "sweep_z": 2.5239e9}
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the kernel sources (csrc/*.h, *.hip, the table generator)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2010_13289_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip", ".py")) and name != "teno_tables.h":
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -198,7 +219,8 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": (MEASURED_TRAFFIC.get(kind) if n == N and kernel_source_digest() == TRAFFIC_SOURCE_DIGEST
+                        else None),
             "avg_launch_ms": avg_s * 1e3,
             "flops_per_launch": flops_launch,
         },
@@ -207,6 +229,7 @@ def main():
         "hbm_alg_frac": (BYTES_PER_CELL_STEP * cells / sec_per_step / 1e9) / PEAK_HBM_GBS,
         "nonsmooth_flag_fraction": nonsmooth / total,
         "state_finite": ok,
+        "kernel_source_digest": kernel_source_digest(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(U_host, grid, args.cpu_seconds)
