@@ -43,8 +43,9 @@ extern "C" {
 #define TENOM_OK 0
 #define TENOM_EINVAL (-1)      /* null pointer, ndim not in {1,2,3}, an used
                                   axis with fewer than K cells, axis >= ndim,
-                                  C_T < 0 or NaN, gamma <= 1 (Euler), dt <= 0
-                                  or non-finite, dx <= 0                   */
+                                  C_T < 0 or NaN (or > 1/(K-2) for classic
+                                  TENO), gamma <= 1 (Euler), dt <= 0 or
+                                  non-finite, dx <= 0                      */
 #define TENOM_EUNSUPPORTED (-2) /* unknown scheme, limiter or system ID     */
 #define TENOM_EWORKSPACE (-3)  /* workspace smaller than
                                   tenom_workspace_bytes()                   */
@@ -63,9 +64,16 @@ extern "C" {
 /* Scheme: number of points K of the full stencil (Sec. 2.1, Table 1).
  * K = 6: candidates S0..S3 on i-2..i+3; K = 8: S0..S5 on i-3..i+4.  The
  * optimal weights d_k are the maximum-order ones (Sec. 3.3), so with every
- * candidate smooth the scheme is the K-point linear scheme. */
+ * candidate smooth the scheme is the K-point linear scheme.
+ * TENOM_SCHEME_8A is the eight-point scheme with the adaptive cutoff of
+ * Sec. 2.4 (Eqs. shock_indicator, cut-off_adjust; xi = 1e-3, C_r = 0.23,
+ * alpha_1 = 10.5, alpha_2 = 3.5): each reconstruction takes
+ * C_T = 10^-floor(beta) in {1e-7 .. 1e-10} from its own stencil values and
+ * the C_T argument of the calls is ignored. */
 #define TENOM_SCHEME_6 6
 #define TENOM_SCHEME_8 8
+#define TENOM_SCHEME_ADAPTIVE 0x100
+#define TENOM_SCHEME_8A (TENOM_SCHEME_8 | TENOM_SCHEME_ADAPTIVE)
 
 /* Filter applied to the candidates the cutoff marks nonsmooth (Sec. 3.2,
  * Eq. mp_flux).  MP: Suresh-Huynh bounds with alpha = 1.25 and the given
@@ -73,9 +81,18 @@ extern "C" {
  * preserving), computed once per face and applied to each nonsmooth
  * candidate.  TVD-type: one limited flux on the fixed stencil centred at i
  * replaces every nonsmooth candidate (Sec. 3.2.3). */
+#define TENOM_LIM_TENO 0       /* none: classic TENO, nonsmooth candidates
+                                  dropped and the weights renormalised
+                                  (Eq. weight_renormalize); needs
+                                  C_T <= 1/(K-2)                           */
 #define TENOM_LIM_MP 1         /* MP, d^M4, beta = 4 (the paper's default) */
 #define TENOM_LIM_TVD_MINMOD 2 /* f_i + minmod(f_i - f_{i-1}, f_{i+1} - f_i)/2 */
 #define TENOM_LIM_TVD5 3       /* Kim & Kim fifth-order TVD, alpha = 2      */
+#define TENOM_LIM_VA 4         /* Van Albada, kappa = 1/3 (Eq. vAflux)     */
+#define TENOM_LIM_MP_M4_B2 5   /* MP, d^M4, beta = 2 (Sec. 4.2.5)          */
+#define TENOM_LIM_MP_MM_B4 6   /* MP, d^MM (Eq. maximal_curvature1), beta 4 */
+#define TENOM_LIM_MP_MM_B2 7   /* MP, d^MM, beta = 2 (Sec. 4.2.5)          */
+#define TENOM_LIM_MP_MM_B1 8   /* MP, d^MM, beta = 1 (Sec. 4.4)            */
 
 /* ---- grid descriptor ---------------------------------------------------- */
 typedef struct tenom_grid {

@@ -22,6 +22,8 @@ _LIB = os.path.join(_HERE, "libtenom_oracle.so")
 # the tests, which pass the same integers to both sides)
 LIM_TENO, LIM_MP, LIM_TVD_MINMOD, LIM_TVD5, LIM_VA = 0, 1, 2, 3, 4
 LIM_MP_M4_B2, LIM_MP_MM_B4, LIM_MP_MM_B2, LIM_MP_MM_B1 = 5, 6, 7, 8
+SCHEME_ADAPTIVE = 0x100           # or-ed into K = 8: the adaptive cutoff (TENO8A)
+SCHEME_8A = 8 | SCHEME_ADAPTIVE
 
 
 def build(force: bool = True) -> str:
@@ -45,7 +47,8 @@ class Trace(C.Structure):
                 ("tau", C.c_double), ("gam", C.c_double * 6), ("chi", C.c_double * 6),
                 ("delta", C.c_int * 6), ("band", C.c_int * 6), ("fmin", C.c_double),
                 ("fmax", C.c_double), ("ftvd", C.c_double), ("fM", C.c_double * 6),
-                ("out", C.c_double)]
+                ("out", C.c_double), ("eta", C.c_double), ("m", C.c_double), ("ct", C.c_double),
+                ("ct_band", C.c_int)]
 
 
 _lib = None
@@ -168,9 +171,10 @@ def _chk(rc, what):
 # ---------------------------------------------------------------------------
 
 def teno_m(K: int, lim: int, C_T: float, v) -> tuple[float, Trace]:
-    """One TENO-M reconstruction at x_{i+1/2} from v = f_{i-K/2+1..i+K/2}."""
+    """One TENO-M reconstruction at x_{i+1/2} from v = f_{i-K/2+1..i+K/2}.
+    K may carry SCHEME_ADAPTIVE (TENO8A: C_T from Sec. 2.4, argument ignored)."""
     v = np.ascontiguousarray(v, dtype=np.float64)
-    assert v.shape == (K,)
+    assert v.shape == (K & 0xFF,)
     tr = Trace()
     out = lib().or_teno_m(K, lim, C_T, _dp(v), C.byref(tr))
     return out, tr

@@ -63,8 +63,20 @@ static const double OR_TVD5_ALPHA = 2.0;
 /* Sec. 3.2.1: kappa = 1/3 restores third order for the Van Albada flux */
 static const double OR_VA_KAPPA = 1.0 / 3.0;
 
+/* Sec. 2.4 (adaptive cutoff of the eight-point schemes): Ren-type indicator
+ * with xi = 1e-3, C_r = 0.23 (Eq. shock_indicator), alpha_1 = 10.5,
+ * alpha_2 = 3.5 (Eq. cut-off_adjust). */
+static const double OR_REN_XI = 1e-3;
+static const double OR_REN_CR = 0.23;
+static const double OR_ADAPT_A1 = 10.5;
+static const double OR_ADAPT_A2 = 3.5;
+
 /* Relative width of the cutoff band reported next to the flags. */
 static const double OR_BAND = 1e-10;
+
+/* Scheme identifiers: the number of points K, optionally with the adaptive
+ * cutoff flag (the eight-point TENO8A scheme of Sec. 2.4). */
+#define OR_SCHEME_ADAPTIVE 0x100
 
 /* Table 1: f_k = sum_m c_m f_m, columns c_{i-3} .. c_{i+4}.  Stored as the
  * printed numerators over the printed denominators. */
@@ -438,15 +450,50 @@ typedef struct {
     double ftvd;     /* TVD-type flux on the fixed stencil */
     double fM[6];    /* Eq. mp_flux */
     double out;
+    double eta;      /* adaptive cutoff: eta_{i+1/2} of Eq. shock_indicator */
+    double m;        /* adaptive cutoff: m */
+    double ct;       /* the C_T actually used */
+    int ct_band;     /* adaptive cutoff: beta within 1e-10 of an integer */
 } or_trace;
 
+/* Eqs. shock_indicator and cut-off_adjust: the cutoff of one face from
+ * f_{i-2} .. f_{i+3} (fv points at f_i). */
+static double or_adaptive_ct(const double* fv, or_trace* tr) {
+    double eps = 0.9 * OR_REN_CR / (1.0 - 0.9 * OR_REN_CR) * OR_REN_XI * OR_REN_XI;
+    double eta_face = 0.0;
+    for (int j = -1; j <= 2; j++) {
+        double dp = fv[j + 1] - fv[j]; /* Delta f_{j+1/2} */
+        double dm = fv[j] - fv[j - 1]; /* Delta f_{j-1/2} */
+        double eta = (fabs(2.0 * dp * dm) + eps) / (dp * dp + dm * dm + eps);
+        eta_face = (j == -1) ? eta : fmin(eta_face, eta);
+    }
+    double m = 1.0 - fmin(1.0, eta_face / OR_REN_CR);
+    double g = pow(1.0 - m, 4.0) * (1.0 + 4.0 * m);
+    double beta = OR_ADAPT_A1 - OR_ADAPT_A2 * (1.0 - g);
+    double fl = floor(beta);
+    tr->eta = eta_face;
+    tr->m = m;
+    /* Rounding can move floor(beta) only where beta is close to one of the
+     * interior integers 8, 9, 10: g lies in [0, 1], so beta >= alpha_1 -
+     * alpha_2 = 7 holds exactly in any rounding and floor(beta) = 7 at the
+     * bottom of the range. */
+    double nb = nearbyint(beta);
+    tr->ct_band = (nb >= 8.0 && nb <= 10.0 && fabs(beta - nb) <= 1e-10) ? 1 : 0;
+    return pow(10.0, -fl);
+}
+
 /* v[0..K-1] hold f at i-K/2+1 .. i+K/2; the result approximates the flux at
- * x_{i+1/2}. */
-double or_teno_m(int K, int lim, double C_T, const double* v, or_trace* tr) {
+ * x_{i+1/2}.  `scheme` is K, or 8 | OR_SCHEME_ADAPTIVE for the adaptive
+ * cutoff of Sec. 2.4 (C_T is then ignored). */
+double or_teno_m(int scheme, int lim, double C_T, const double* v, or_trace* tr) {
     or_trace loc;
     if (!tr) tr = &loc;
     memset(tr, 0, sizeof(*tr));
-    if (or_init() != 0 || (K != 6 && K != 8)) return NAN;
+    int K = scheme & 0xff;
+    int adaptive = (scheme & OR_SCHEME_ADAPTIVE) != 0;
+    if (or_init() != 0 || (K != 6 && K != 8) || (adaptive && K != 8)) return NAN;
+    if (adaptive) C_T = or_adaptive_ct(v + K / 2 - 1, tr);
+    tr->ct = C_T;
     int nk = K - 2;
     int c0 = K / 2 - 1; /* index of f_i in v */
     const double* dk = g_d[K == 6 ? 0 : 1];
@@ -666,7 +713,7 @@ int or_roe_eigenvectors(int ndim, double gamma, int ax, const double* UL, const 
  * (0 = +, 1 = -) and component, the bit mask of delta_k / band hits. */
 static int or_face_flux(const or_grid* g, const or_scheme* sc, const or_state* s, int ax, const int* p,
                         double* Fout, uint8_t* flags, uint8_t* band) {
-    int K = sc->K, h = K / 2, nf = or_nfields(g);
+    int K = sc->K & 0xff, h = K / 2, nf = or_nfields(g);
     double Uc[8][5], Fc[8][5], lam[8];
     for (int m = 0; m < K; m++) {
         int q[3] = {p[0], p[1], p[2]};
@@ -705,16 +752,16 @@ static int or_face_flux(const or_grid* g, const or_scheme* sc, const or_state* s
         or_trace tp, tm;
         double mir[8];
         for (int m = 0; m < K; m++) mir[m] = gm[c][K - 1 - m];
-        double fplus = or_teno_m(K, sc->lim, sc->C_T, gp[c], &tp);
-        double fminus = or_teno_m(K, sc->lim, sc->C_T, mir, &tm);
+        double fplus = or_teno_m(sc->K, sc->lim, sc->C_T, gp[c], &tp);
+        double fminus = or_teno_m(sc->K, sc->lim, sc->C_T, mir, &tm);
         fc[c] = fplus + fminus;
         if (flags || band) {
             uint8_t bp = 0, bm = 0, np = 0, nm = 0;
             for (int k = 0; k < K - 2; k++) {
                 bp |= (uint8_t)(tp.delta[k] << k);
                 bm |= (uint8_t)(tm.delta[k] << k);
-                np |= (uint8_t)(tp.band[k] << k);
-                nm |= (uint8_t)(tm.band[k] << k);
+                np |= (uint8_t)((tp.band[k] | tp.ct_band) << k);
+                nm |= (uint8_t)((tm.band[k] | tm.ct_band) << k);
             }
             if (flags) {
                 flags[c] = bp;
@@ -762,7 +809,9 @@ static int or_dudt_cell(const or_grid* g, const or_scheme* sc, const or_state* s
 static int or_check(const or_grid* g, const or_scheme* sc) {
     if (or_init() != 0) return -10;
     if (!g || g->ndim < 1 || g->ndim > 3) return -1;
-    if (sc->K != 6 && sc->K != 8) return -2;
+    int k = sc->K & 0xff;
+    if (k != 6 && k != 8) return -2;
+    if ((sc->K & ~(0xff | OR_SCHEME_ADAPTIVE)) || ((sc->K & OR_SCHEME_ADAPTIVE) && k != 8)) return -2;
     for (int d = 0; d < g->ndim; d++)
         if (g->n[d] < 1) return -1;
     if (g->system != 0 && g->system != 1) return -2;
@@ -973,7 +1022,7 @@ int or_rk3_points(const or_grid* g, int K, int lim, double C_T, double gamma, do
     or_scheme sc = {K, lim, C_T, gamma};
     int rc = or_check(g, &sc);
     if (rc) return rc;
-    int nf = or_nfields(g), h = K / 2;
+    int nf = or_nfields(g), h = (K & 0xff) / 2;
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
     for (long t = 0; t < npts; t++) {

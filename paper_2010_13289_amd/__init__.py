@@ -21,7 +21,10 @@ OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 SYS_SCALAR, SYS_EULER = 0, 1
 SCHEME_6, SCHEME_8 = 6, 8
-LIM_MP, LIM_TVD_MINMOD, LIM_TVD5 = 1, 2, 3
+SCHEME_ADAPTIVE = 0x100
+SCHEME_8A = SCHEME_8 | SCHEME_ADAPTIVE   # eight points, adaptive cutoff (TENO8A)
+LIM_TENO, LIM_MP, LIM_TVD_MINMOD, LIM_TVD5, LIM_VA = 0, 1, 2, 3, 4
+LIM_MP_M4_B2, LIM_MP_MM_B4, LIM_MP_MM_B2, LIM_MP_MM_B1 = 5, 6, 7, 8
 KERNEL_KINDS = ("faces", "sweep_x", "sweep_y", "sweep_z")
 
 SYMBOLS = (

@@ -5,9 +5,10 @@
 
 #include "teno_kernels.h"
 
-#define TENOM_DECLARE_UNIT(NF, K)                                                   \
-  hipError_t tenom_faces_nf##NF##_k##K(int lim, const tenom::FacesLaunch& a);      \
-  hipError_t tenom_sweep_nf##NF##_k##K(int lim, const tenom::SweepLaunch& a);
+// lim: limiter kind (tenom::LIM_*), adapt: 1 for the adaptive cutoff (K = 8)
+#define TENOM_DECLARE_UNIT(NF, K)                                                          \
+  hipError_t tenom_faces_nf##NF##_k##K(int lim, int adapt, const tenom::FacesLaunch& a);  \
+  hipError_t tenom_sweep_nf##NF##_k##K(int lim, int adapt, const tenom::SweepLaunch& a);
 
 TENOM_DECLARE_UNIT(1, 6)
 TENOM_DECLARE_UNIT(1, 8)

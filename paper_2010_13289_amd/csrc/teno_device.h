@@ -22,8 +22,21 @@ namespace tenom {
 constexpr double kEps = 1e-40;
 constexpr double kEps2x = 4.0 * kEps;
 
-// Limiter identifiers of the C ABI (values of TENOM_LIM_*).
-enum : int { LIM_MP = 1, LIM_TVD_MINMOD = 2, LIM_TVD5 = 3 };
+// Limiter kinds (template values).  The C ABI's limiter IDs map onto them:
+// MP with d^M4 (IDs 1, 5) and with d^MM (IDs 6, 7, 8) differ only in the
+// runtime beta of Eq. large_curvature.
+enum : int { LIM_TENO = 0, LIM_MP = 1, LIM_TVD_MINMOD = 2, LIM_TVD5 = 3, LIM_VA = 4, LIM_MP_MM = 6 };
+
+// Runtime parameters of one reconstruction.
+struct TenoParams {
+  double C_T;       // cutoff (ignored with the adaptive cutoff)
+  double mp_beta3;  // beta / 3 of Eq. large_curvature (MP limiters)
+};
+
+// Sec. 2.4: Ren-type indicator (xi = 1e-3, C_r = 0.23) and the cutoff
+// adaptation (alpha_1 = 10.5, alpha_2 = 3.5) of the eight-point schemes.
+constexpr double kRenCr = 0.23;
+constexpr double kRenEps = 0.9 * kRenCr / (1.0 - 0.9 * kRenCr) * 1e-3 * 1e-3;
 
 // minmod of two / four arguments (Eqs. minmod222, minmod444), branch-free:
 // the smallest-magnitude argument if all share a sign, else 0.
@@ -62,8 +75,8 @@ __device__ __forceinline__ double rcp1(double x) {
 // every step is homogeneous, with eps scaled to match, so the result is
 // exactly twice the reconstruction of the halved values.
 // ---------------------------------------------------------------------------
-template <int K, int LIM, bool FLAGS>
-__device__ __forceinline__ double teno_m(const double (&v)[K], double C_T, uint32_t& bits) {
+template <int K, int LIM, bool FLAGS, bool ADAPT>
+__device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams& tp, uint32_t& bits) {
   using T = TenoTables<K>;
   constexpr int NK = K - 2;
   constexpr int C0 = K / 2 - 1;  // index of v_i
@@ -71,6 +84,28 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], double C_T, uint3
   double D[K - 1];
 #pragma unroll
   for (int j = 0; j < K - 1; ++j) D[j] = v[j + 1] - v[j];
+
+  double C_T = tp.C_T;
+  if constexpr (ADAPT) {
+    // Eq. shock_indicator: eta at cells i-1 .. i+2 (eps scaled by 4 for the
+    // doubled values), the minimum, m = 1 - min(1, eta / C_r)
+    double eta = 0.0;
+#pragma unroll
+    for (int j = C0 - 1; j <= C0 + 2; ++j) {
+      const double a = D[j], b = D[j - 1];
+      const double num = fabs(2.0 * a * b) + 4.0 * kRenEps;
+      const double den = fma(a, a, fma(b, b, 4.0 * kRenEps));
+      const double e = num * rcp1(den);
+      eta = (j == C0 - 1) ? e : fmin(eta, e);
+    }
+    const double m = 1.0 - fmin(1.0, eta * (1.0 / kRenCr));
+    // Eq. cut-off_adjust: g = (1-m)^4 (1+4m), beta = 10.5 - 3.5 (1 - g),
+    // C_T = 10^-floor(beta) with floor(beta) in {7, 8, 9, 10}
+    const double om = 1.0 - m, om2 = om * om;
+    const double g = om2 * om2 * fma(4.0, m, 1.0);
+    const double fl = floor(fma(-3.5, 1.0 - g, 10.5));
+    C_T = fl >= 10.0 ? 1e-10 : (fl >= 9.0 ? 1e-9 : (fl >= 8.0 ? 1e-8 : 1e-7));
+  }
 
   // candidate fluxes (Table 1), minus v_i
   double c[NK];
@@ -97,17 +132,24 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], double C_T, uint3
   const double dm = D[C0 - 1];  // f_i - f_{i-1}
   const double dp = D[C0];      // f_{i+1} - f_i
   double lo = 0.0, hi = 0.0, ftvd = 0.0;
-  if constexpr (LIM == LIM_MP) {
-    // curvatures (Eq. curvature) and d^M4 at i -+ 1/2 (Eq. maximal_curvature)
+  if constexpr (LIM == LIM_MP || LIM == LIM_MP_MM) {
+    // curvatures (Eq. curvature); d^M4 (Eq. maximal_curvature) or d^MM
+    // (Eq. maximal_curvature1) at i -+ 1/2
     const double d_im1 = D[C0 - 1] - D[C0 - 2];
     const double d_i = D[C0] - D[C0 - 1];
     const double d_ip1 = D[C0 + 1] - D[C0];
-    const double dR = minmod4(4.0 * d_i - d_ip1, 4.0 * d_ip1 - d_i, d_i, d_ip1);
-    const double dL = minmod4(4.0 * d_im1 - d_i, 4.0 * d_i - d_im1, d_im1, d_i);
-    // Eqs. upper_limiter, median_value, large_curvature (alpha 1.25, beta 4)
+    double dR, dL;
+    if constexpr (LIM == LIM_MP) {
+      dR = minmod4(4.0 * d_i - d_ip1, 4.0 * d_ip1 - d_i, d_i, d_ip1);
+      dL = minmod4(4.0 * d_im1 - d_i, 4.0 * d_i - d_im1, d_im1, d_i);
+    } else {
+      dR = minmod2(d_i, d_ip1);
+      dL = minmod2(d_im1, d_i);
+    }
+    // Eqs. upper_limiter, median_value, large_curvature (alpha 1.25)
     const double ul = 1.25 * dm;
     const double md = 0.5 * dp - 0.5 * dR;
-    const double lc = fma(4.0 / 3.0, dL, 0.5 * dm);
+    const double lc = fma(tp.mp_beta3, dL, 0.5 * dm);
     // Eq. value_min_max; 0 (= f_i) lies in both brackets, so lo <= 0 <= hi
     lo = fmax(fmin(fmin(0.0, dp), md), fmin(fmin(0.0, ul), lc));
     hi = fmin(fmax(fmax(0.0, dp), md), fmax(fmax(0.0, ul), lc));
@@ -120,23 +162,44 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], double C_T, uint3
     const double up = fmax(0.0, fmin(fmin(2.0 * dm, 2.0 * dp), B));
     const double dn = fmin(0.0, fmax(fmax(2.0 * dm, 2.0 * dp), B));
     ftvd = 0.5 * (dm > 0.0 ? up : (dm < 0.0 ? dn : 0.0));
+  } else if constexpr (LIM == LIM_VA) {
+    // Eqs. van_Albada_limiter, slop_ratio, vAflux with kappa = 1/3:
+    // phi = 2 r/(r^2 + 1) = 2 d+ d- / (d+^2 + d-^2), 0 when both vanish
+    const double den = fma(dp, dp, dm * dm);
+    const double phi = den > 0.0 ? 2.0 * dp * dm * rcp(den) : 0.0;
+    const double kp = phi * (1.0 / 3.0);
+    ftvd = 0.25 * phi * fma(1.0 - kp, dm, (1.0 + kp) * dp);
   }
 
-  // assembly with the optimal weights, no renormalisation (Eq. reconstuction)
-  double acc = 0.0;
+  if constexpr (LIM == LIM_TENO) {
+    // classic TENO: nonsmooth candidates dropped, weights renormalised
+    // (Eq. weight_renormalize); at least one candidate is smooth for C_T <= 1/(K-2)
+    double num = 0.0, den = 0.0;
 #pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    const bool smooth = !(g[k] < thr);
-    double lim;
-    if constexpr (LIM == LIM_MP) {
-      lim = fmin(fmax(c[k], lo), hi);  // median(f_k, f_min, f_max), lo <= hi
-    } else {
-      lim = ftvd;
+    for (int k = 0; k < NK; ++k) {
+      const bool smooth = !(g[k] < thr);
+      num = smooth ? fma(T::d(k), c[k], num) : num;
+      den = smooth ? den + T::d(k) : den;
+      if constexpr (FLAGS) bits |= (smooth ? 1u : 0u) << k;
     }
-    acc = fma(T::d(k), smooth ? c[k] : lim, acc);
-    if constexpr (FLAGS) bits |= (smooth ? 1u : 0u) << k;
+    return v[C0] + num * rcp(den);
+  } else {
+    // assembly with the optimal weights, no renormalisation (Eq. reconstuction)
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const bool smooth = !(g[k] < thr);
+      double lim;
+      if constexpr (LIM == LIM_MP || LIM == LIM_MP_MM) {
+        lim = fmin(fmax(c[k], lo), hi);  // median(f_k, f_min, f_max), lo <= hi
+      } else {
+        lim = ftvd;
+      }
+      acc = fma(T::d(k), smooth ? c[k] : lim, acc);
+      if constexpr (FLAGS) bits |= (smooth ? 1u : 0u) << k;
+    }
+    return v[C0] + acc;
   }
-  return v[C0] + acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -180,20 +243,30 @@ __device__ __forceinline__ void lf_split2(double f, double alpha, double u, doub
 // ---------------------------------------------------------------------------
 
 // physical flux along the normal and signal speed |u_n| + c
+//
+// The per-cell arithmetic here, in roe_input and in the characteristic
+// projection is compiled without contraction and every fused multiply-add
+// is written out: each cell then goes through the same roundings wherever
+// it sits in a stencil, so cells with equal values (a transmissive ghost
+// region, a uniform state) give exactly equal split values, zero
+// differences and beta_k = 0, whatever the instantiation around them.
 template <int NF>
 __device__ __forceinline__ void cell_physics(const double (&X)[NF], double gamma, double (&F)[NF], double& lam) {
+#pragma clang fp contract(off)
   constexpr int ND = NF - 2;
+  const double gm1 = gamma - 1.0;
   const double rinv = rcp(X[0]);
   const double un = X[1] * rinv;
   double mu = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) mu = fma(X[1 + d], X[1 + d], mu);
-  const double p = (gamma - 1.0) * fma(-0.5 * rinv, mu, X[NF - 1]);
+  const double e = fma(-0.5 * rinv, mu, X[NF - 1]);  // internal energy per volume
+  const double p = gm1 * e;
   F[0] = X[1];
   F[1] = fma(X[1], un, p);
 #pragma unroll
   for (int t = 1; t < ND; ++t) F[1 + t] = X[1 + t] * un;
-  F[NF - 1] = (X[NF - 1] + p) * un;
+  F[NF - 1] = fma(gm1, e, X[NF - 1]) * un;
   lam = fabs(un) + sqrt(gamma * p * rinv);
 }
 
@@ -207,6 +280,7 @@ struct RoeIn {
 
 template <int NF>
 __device__ __forceinline__ void roe_input(const double (&X)[NF], double gamma, RoeIn<NF>& r) {
+#pragma clang fp contract(off)
   constexpr int ND = NF - 2;
   const double rinv = rcp(X[0]);
   double q2 = 0.0;
@@ -215,8 +289,8 @@ __device__ __forceinline__ void roe_input(const double (&X)[NF], double gamma, R
     r.u[d] = X[1 + d] * rinv;
     q2 = fma(r.u[d], r.u[d], q2);
   }
-  const double p = (gamma - 1.0) * fma(-0.5 * X[0], q2, X[NF - 1]);
-  r.H = (X[NF - 1] + p) * rinv;
+  const double e = fma(-0.5 * X[0], q2, X[NF - 1]);
+  r.H = fma(gamma - 1.0, e, X[NF - 1]) * rinv;  // (E + p) / rho
   r.rs = sqrt(X[0]);
 }
 
@@ -227,8 +301,8 @@ __device__ __forceinline__ void roe_input(const double (&X)[NF], double gamma, R
 // Characteristic fields are ordered (u_n - c, entropy, shear waves in
 // ascending axis order, u_n + c).
 // ---------------------------------------------------------------------------
-template <int NF, int K, int LIM, bool FLAGS, class P>
-__device__ __forceinline__ void euler_face(P& prov, double gamma, double C_T, double (&Fh)[NF],
+template <int NF, int K, int LIM, bool FLAGS, bool ADAPT, class P>
+__device__ __forceinline__ void euler_face(P& prov, double gamma, const TenoParams& tp, double (&Fh)[NF],
                                            uint32_t (&bits)[2][NF]) {
   constexpr int ND = NF - 2;
   const double gm1 = gamma - 1.0;
@@ -256,17 +330,19 @@ __device__ __forceinline__ void euler_face(P& prov, double gamma, double C_T, do
   const double b2 = 0.5 * q2t * b1;
 
   // left eigenvectors applied to a conservative vector X
+  // (no contraction: the same roundings for every stencil cell)
   auto project = [&](const double (&X)[NF], double (&w)[NF]) {
+#pragma clang fp contract(off)
     double um = 0.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) um = fma(ut[d], X[1 + d], um);
     const double A = fma(b2, X[0], b1 * (X[NF - 1] - um));
-    const double B = fma(ut[0], X[0], -X[1]) * cinv;
-    w[0] = 0.5 * (A + B);
+    const double Bn = fma(ut[0], X[0], -X[1]);  // B = Bn / c
+    w[0] = 0.5 * fma(Bn, cinv, A);
     w[1] = X[0] - A;
 #pragma unroll
     for (int t = 1; t < ND; ++t) w[1 + t] = fma(-ut[t], X[0], X[1 + t]);
-    w[NF - 1] = 0.5 * (A - B);
+    w[NF - 1] = 0.5 * fma(-Bn, cinv, A);
   };
 
   // stencil cells: characteristic projections of U and F, Rusanov alpha
@@ -289,7 +365,7 @@ __device__ __forceinline__ void euler_face(P& prov, double gamma, double C_T, do
 #pragma unroll
     for (int m = 0; m < K; ++m) lf_split2(G[m][q], alpha, W[m][q], vp[m], vm[K - 1 - m]);
     bits[0][q] = bits[1][q] = 0u;
-    fc[q] = 0.5 * (teno_m<K, LIM, FLAGS>(vp, C_T, bits[0][q]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1][q]));
+    fc[q] = 0.5 * (teno_m<K, LIM, FLAGS, ADAPT>(vp, tp, bits[0][q]) + teno_m<K, LIM, FLAGS, ADAPT>(vm, tp, bits[1][q]));
   }
 
   // back to conservative variables with the right eigenvectors
@@ -311,8 +387,8 @@ __device__ __forceinline__ void euler_face(P& prov, double gamma, double C_T, do
 // Scalar advection face flux from a provider: prov.value(m) = u of window
 // cell m.  f = a u, Rusanov split with alpha = |a|.
 // ---------------------------------------------------------------------------
-template <int K, int LIM, bool FLAGS, class P>
-__device__ __forceinline__ void scalar_face(P& prov, double a, double C_T, double& F, uint32_t (&bits)[2]) {
+template <int K, int LIM, bool FLAGS, bool ADAPT, class P>
+__device__ __forceinline__ void scalar_face(P& prov, double a, const TenoParams& tp, double& F, uint32_t (&bits)[2]) {
   const double alpha = fabs(a);
   double vp[K], vm[K];
 #pragma unroll
@@ -321,25 +397,25 @@ __device__ __forceinline__ void scalar_face(P& prov, double a, double C_T, doubl
     lf_split2(a * u, alpha, u, vp[m], vm[K - 1 - m]);  // f- side stored mirrored
   }
   bits[0] = bits[1] = 0u;
-  F = 0.5 * (teno_m<K, LIM, FLAGS>(vp, C_T, bits[0]) + teno_m<K, LIM, FLAGS>(vm, C_T, bits[1]));
+  F = 0.5 * (teno_m<K, LIM, FLAGS, ADAPT>(vp, tp, bits[0]) + teno_m<K, LIM, FLAGS, ADAPT>(vm, tp, bits[1]));
 }
 
 struct FaceParams {
   double gamma;
-  double C_T;
   double adv;  // advection speed along the axis (scalar system)
+  TenoParams tp;
 };
 
 // Dispatch on the system: NF == 1 is scalar advection, otherwise Euler.
-template <int NF, int K, int LIM, bool FLAGS, class P>
+template <int NF, int K, int LIM, bool ADAPT, bool FLAGS, class P>
 __device__ __forceinline__ void face_flux(P& prov, const FaceParams& fp, double (&F)[NF], uint32_t (&bits)[2][NF]) {
   if constexpr (NF == 1) {
     uint32_t b[2];
-    scalar_face<K, LIM, FLAGS>(prov, fp.adv, fp.C_T, F[0], b);
+    scalar_face<K, LIM, FLAGS, ADAPT>(prov, fp.adv, fp.tp, F[0], b);
     bits[0][0] = b[0];
     bits[1][0] = b[1];
   } else {
-    euler_face<NF, K, LIM, FLAGS>(prov, fp.gamma, fp.C_T, F, bits);
+    euler_face<NF, K, LIM, FLAGS, ADAPT>(prov, fp.gamma, fp.tp, F, bits);
   }
 }
 

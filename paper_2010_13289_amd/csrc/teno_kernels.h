@@ -87,7 +87,7 @@ __device__ __forceinline__ void epi_store(const SweepParams<NF>& p, long N, long
 }
 
 // ---------------------------------------------------------------------------
-template <int NF, int K, int LIM>
+template <int NF, int K, int LIM, bool ADAPT>
 __global__ __launch_bounds__(256) void k_faces(const double* __restrict__ U, double* __restrict__ Fhat,
                                                uint8_t* __restrict__ flags, int axis, int nx, int ny, int nz,
                                                int bc, int fld0, int fld1, int fld2, int fld3, int fld4,
@@ -120,14 +120,14 @@ __global__ __launch_bounds__(256) void k_faces(const double* __restrict__ U, dou
   double F[NF];
   uint32_t bits[2][NF];
   if (flags) {
-    face_flux<NF, K, LIM, true>(prov, fp, F, bits);
+    face_flux<NF, K, LIM, ADAPT, true>(prov, fp, F, bits);
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
       flags[(long)q * nfaces + t] = (uint8_t)bits[0][q];
       flags[(long)(NF + q) * nfaces + t] = (uint8_t)bits[1][q];
     }
   } else {
-    face_flux<NF, K, LIM, false>(prov, fp, F, bits);
+    face_flux<NF, K, LIM, ADAPT, false>(prov, fp, F, bits);
   }
 #pragma unroll
   for (int q = 0; q < NF; ++q) Fhat[(long)fld[q] * nfaces + t] = F[q];
@@ -168,7 +168,7 @@ struct StagedCells {
   __device__ __forceinline__ double value(int m) const { return at(0, c0 + m); }
 };
 
-template <int NF, int K, int LIM>
+template <int NF, int K, int LIM, bool ADAPT>
 __global__ __launch_bounds__(256) void k_sweep_row(SweepParams<NF> p) {
   constexpr int NC = 256 + K - 1;  // staged cells per segment
   constexpr int NE = RowStage<NF>::NE;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_sweep_row(SweepParams<NF> p) {
   if (t < nface) {
     StagedCells<NF, K> prov{stage, NC, t};
     uint32_t bits[2][NF];
-    face_flux<NF, K, LIM, false>(prov, p.fp, F, bits);
+    face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F, bits);
   }
   // stage state of this thread's cell (staged at t + K/2), copied before the
   // staging array is reused
@@ -279,7 +279,7 @@ struct MarchShape {
   static constexpr int LINES = (K * NF * 8 * 64 * 4 <= 65536) ? 4 : 2;
 };
 
-template <int NF, int K, int LIM>
+template <int NF, int K, int LIM, bool ADAPT>
 __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march(SweepParams<NF> p, int axis) {
   constexpr int LINES = MarchShape<NF, K>::LINES;
   constexpr int T = 64 * LINES;
@@ -330,7 +330,7 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
       RingCells<NF, K> prov{ring, T, tid, slot0, p.fp.gamma};
       prov.load(K / 2 - 1, us);  // cell j - 1 is window cell K/2 - 1 of face j
       uint32_t bits[2][NF];
-      face_flux<NF, K, LIM, false>(prov, p.fp, F, bits);
+      face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F, bits);
     }
     if (more) {
 #pragma unroll
@@ -377,16 +377,16 @@ struct SweepLaunch {
   hipStream_t stream;
 };
 
-template <int NF, int K, int LIM>
+template <int NF, int K, int LIM, bool ADAPT>
 hipError_t launch_faces(const FacesLaunch& a) {
   const long nfaces = (long)(a.nx + (a.axis == 0)) * (a.ny + (a.axis == 1)) * (a.nz + (a.axis == 2));
   const unsigned blocks = (unsigned)((nfaces + 255) / 256);
-  hipLaunchKernelGGL((k_faces<NF, K, LIM>), dim3(blocks), dim3(256), 0, a.stream, a.U, a.Fhat, a.flags, a.axis,
+  hipLaunchKernelGGL((k_faces<NF, K, LIM, ADAPT>), dim3(blocks), dim3(256), 0, a.stream, a.U, a.Fhat, a.flags, a.axis,
                      a.nx, a.ny, a.nz, a.bc, a.fld[0], a.fld[1], a.fld[2], a.fld[3], a.fld[4], a.fp);
   return hipGetLastError();
 }
 
-template <int NF, int K, int LIM>
+template <int NF, int K, int LIM, bool ADAPT>
 hipError_t launch_sweep(const SweepLaunch& a) {
   SweepParams<NF> p;
   p.U = a.U;
@@ -409,7 +409,7 @@ hipError_t launch_sweep(const SweepLaunch& a) {
     p.seg = (a.bc == 0 && a.nx <= 256) ? a.nx : 255;
     p.nseg = (p.n + p.seg - 1) / p.seg;
     const long blocks = (long)p.nseg * a.ny * a.nz;
-    hipLaunchKernelGGL((k_sweep_row<NF, K, LIM>), dim3((unsigned)blocks), dim3(256), 0, a.stream, p);
+    hipLaunchKernelGGL((k_sweep_row<NF, K, LIM, ADAPT>), dim3((unsigned)blocks), dim3(256), 0, a.stream, p);
   } else {
     p.n = (a.axis == 1) ? a.ny : a.nz;
     p.seg = a.seg >= p.n ? p.n : a.seg;
@@ -417,7 +417,7 @@ hipError_t launch_sweep(const SweepLaunch& a) {
     const int n_other = (a.axis == 1) ? a.nz : a.ny;
     constexpr int LINES = MarchShape<NF, K>::LINES;
     dim3 grid((a.nx + 63) / 64, (n_other + LINES - 1) / LINES, p.nseg);
-    hipLaunchKernelGGL((k_sweep_march<NF, K, LIM>), grid, dim3(64, LINES), 0, a.stream, p, a.axis);
+    hipLaunchKernelGGL((k_sweep_march<NF, K, LIM, ADAPT>), grid, dim3(64, LINES), 0, a.stream, p, a.axis);
   }
   return hipGetLastError();
 }

@@ -70,14 +70,48 @@ int check_grid(const tenom_grid* g, int K) {
   return TENOM_OK;
 }
 
+// scheme -> K (0 if invalid) and the adaptive-cutoff flag
+int scheme_K(int scheme, bool* adaptive) {
+  const int K = scheme & 0xff;
+  *adaptive = (scheme & TENOM_SCHEME_ADAPTIVE) != 0;
+  if (scheme & ~(0xff | TENOM_SCHEME_ADAPTIVE)) return 0;
+  if (K != 6 && K != 8) return 0;
+  if (*adaptive && K != 8) return 0;
+  return K;
+}
+
+// limiter ID -> kernel limiter kind and the beta of Eq. large_curvature
+bool limiter_kind(int id, int* kind, double* beta) {
+  *beta = 4.0;
+  switch (id) {
+    case TENOM_LIM_TENO: *kind = LIM_TENO; return true;
+    case TENOM_LIM_MP: *kind = LIM_MP; return true;
+    case TENOM_LIM_TVD_MINMOD: *kind = LIM_TVD_MINMOD; return true;
+    case TENOM_LIM_TVD5: *kind = LIM_TVD5; return true;
+    case TENOM_LIM_VA: *kind = LIM_VA; return true;
+    case TENOM_LIM_MP_M4_B2: *kind = LIM_MP; *beta = 2.0; return true;
+    case TENOM_LIM_MP_MM_B4: *kind = LIM_MP_MM; return true;
+    case TENOM_LIM_MP_MM_B2: *kind = LIM_MP_MM; *beta = 2.0; return true;
+    case TENOM_LIM_MP_MM_B1: *kind = LIM_MP_MM; *beta = 1.0; return true;
+    default: return false;
+  }
+}
+
 int check_scheme(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma) {
-  if (scheme != TENOM_SCHEME_6 && scheme != TENOM_SCHEME_8)
-    return fail(TENOM_EUNSUPPORTED, "unknown scheme %d (use 6 or 8)", scheme);
-  if (limiter != TENOM_LIM_MP && limiter != TENOM_LIM_TVD_MINMOD && limiter != TENOM_LIM_TVD5)
-    return fail(TENOM_EUNSUPPORTED, "unknown limiter %d", limiter);
-  int rc = check_grid(g, scheme);
+  bool adaptive;
+  const int K = scheme_K(scheme, &adaptive);
+  if (!K) return fail(TENOM_EUNSUPPORTED, "unknown scheme %d (use 6, 8 or TENOM_SCHEME_8A)", scheme);
+  int kind;
+  double beta;
+  if (!limiter_kind(limiter, &kind, &beta)) return fail(TENOM_EUNSUPPORTED, "unknown limiter %d", limiter);
+  int rc = check_grid(g, K);
   if (rc) return rc;
-  if (!(C_T >= 0.0)) return fail(TENOM_EINVAL, "C_T must be >= 0 (got %g)", C_T);
+  if (!adaptive) {
+    if (!(C_T >= 0.0)) return fail(TENOM_EINVAL, "C_T must be >= 0 (got %g)", C_T);
+    // classic TENO keeps at least one candidate only if C_T <= 1/(K-2)
+    if (limiter == TENOM_LIM_TENO && C_T > 1.0 / (K - 2))
+      return fail(TENOM_EINVAL, "classic TENO needs C_T <= 1/(K-2) (got %g)", C_T);
+  }
   if (g->system == TENOM_SYS_EULER && !(gamma > 1.0 && isfinite(gamma)))
     return fail(TENOM_EINVAL, "gamma must be finite and > 1 (got %g)", gamma);
   return TENOM_OK;
@@ -96,16 +130,20 @@ void field_map(const tenom_grid* g, int axis, int (&fld)[5]) {
   fld[nd + 1] = nd + 1;
 }
 
-FaceParams face_params(const tenom_grid* g, int axis, double C_T, double gamma) {
+FaceParams face_params(const tenom_grid* g, int axis, int limiter, double C_T, double gamma) {
   FaceParams fp;
+  int kind;
+  double beta;
+  limiter_kind(limiter, &kind, &beta);
   fp.gamma = gamma;
-  fp.C_T = C_T;
   fp.adv = (g->system == TENOM_SYS_SCALAR) ? g->adv[axis] : 0.0;
+  fp.tp.C_T = C_T;
+  fp.tp.mp_beta3 = beta / 3.0;
   return fp;
 }
 
-using FacesFn = hipError_t (*)(int, const FacesLaunch&);
-using SweepFn = hipError_t (*)(int, const SweepLaunch&);
+using FacesFn = hipError_t (*)(int, int, const FacesLaunch&);
+using SweepFn = hipError_t (*)(int, int, const SweepLaunch&);
 
 bool pick(int nf, int K, FacesFn* f, SweepFn* s) {
 #define TENOM_CASE(NF, KK)                      \
@@ -191,11 +229,16 @@ int march_segment(int n, int nx, int n_other) {
 
 // Launch one sweep of `axis` with the given epilogue.  In the RK modes the
 // stage state U_s of the update is U, the state the stencils read.
-int sweep(const tenom_grid* g, int K, int limiter, double C_T, double gamma, int axis, const double* U, double* R,
-          const double* U0, double* Uout, double a, double b, double dt, int mode, hipStream_t stream) {
+int sweep(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma, int axis, const double* U,
+          double* R, const double* U0, double* Uout, double a, double b, double dt, int mode, hipStream_t stream) {
   FacesFn ff;
   SweepFn sf;
   const int nf = nfields(g);
+  bool adaptive;
+  const int K = scheme_K(scheme, &adaptive);
+  int kind;
+  double beta;
+  limiter_kind(limiter, &kind, &beta);
   if (!pick(nf, K, &ff, &sf)) return fail(TENOM_EUNSUPPORTED, "no kernel for %d fields, K = %d", nf, K);
   const Dims d = dims(g);
   SweepLaunch L;
@@ -216,12 +259,12 @@ int sweep(const tenom_grid* g, int K, int limiter, double C_T, double gamma, int
   const int n_axis = axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
   L.seg = axis == 0 ? 0 : march_segment(n_axis, d.nx, axis == 1 ? d.nz : d.ny);
   field_map(g, axis, L.fld);
-  L.fp = face_params(g, axis, C_T, gamma);
+  L.fp = face_params(g, axis, limiter, C_T, gamma);
   L.stream = stream;
   hipError_t e;
   {
     ProfScope ps(1 + axis, stream);
-    e = sf(limiter, L);
+    e = sf(kind, adaptive ? 1 : 0, L);
   }
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
   return TENOM_OK;
@@ -334,7 +377,12 @@ int tenom_reconstruct_faces(const tenom_grid* grid, int scheme, int limiter, dou
   if (!U || !Fhat) return fail(TENOM_EINVAL, "U and Fhat must not be NULL");
   FacesFn ff;
   SweepFn sf;
-  if (!pick(nfields(grid), scheme, &ff, &sf)) return fail(TENOM_EUNSUPPORTED, "no kernel");
+  bool adaptive;
+  const int K = scheme_K(scheme, &adaptive);
+  int kind;
+  double beta;
+  limiter_kind(limiter, &kind, &beta);
+  if (!pick(nfields(grid), K, &ff, &sf)) return fail(TENOM_EUNSUPPORTED, "no kernel");
   const Dims d = dims(grid);
   FacesLaunch L;
   L.U = U;
@@ -346,12 +394,12 @@ int tenom_reconstruct_faces(const tenom_grid* grid, int scheme, int limiter, dou
   L.nz = d.nz;
   L.bc = grid->bc[axis];
   field_map(grid, axis, L.fld);
-  L.fp = face_params(grid, axis, C_T, gamma);
+  L.fp = face_params(grid, axis, limiter, C_T, gamma);
   L.stream = (hipStream_t)stream;
   hipError_t e;
   {
     ProfScope ps(0, L.stream);
-    e = ff(limiter, L);
+    e = ff(kind, adaptive ? 1 : 0, L);
   }
   if (e != hipSuccess) return hip_fail(e, "face kernel launch");
   return TENOM_OK;
@@ -376,8 +424,9 @@ int tenom_flux_divergence(const tenom_grid* grid, int scheme, int limiter, doubl
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t tenom_workspace_bytes(const tenom_grid* grid, int scheme) {
-  if (check_grid(grid, scheme == TENOM_SCHEME_8 ? 8 : 6) != TENOM_OK) return 0;
-  if (scheme != TENOM_SCHEME_6 && scheme != TENOM_SCHEME_8) return 0;
+  bool adaptive;
+  const int K = scheme_K(scheme, &adaptive);
+  if (!K || check_grid(grid, K) != TENOM_OK) return 0;
   const size_t state = align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
   return 3 * state;  // divergence accumulator R, stage states U1 and U2
 }

@@ -1,4 +1,7 @@
-// One instantiation unit: all limiters for TENOM_NF fields and K = TENOM_K.
+// One instantiation unit: every limiter kind (and, for K = 8, the adaptive
+// cutoff) for TENOM_NF fields and K = TENOM_K.
+#include <type_traits>
+
 #include "dispatch.h"
 
 #ifndef TENOM_NF
@@ -17,20 +20,34 @@
 
 using namespace tenom;
 
-hipError_t TENOM_EXPAND_FACES(TENOM_NF, TENOM_K)(int lim, const FacesLaunch& a) {
+template <bool ADAPT, class Launch, class Fn>
+static hipError_t by_limiter(int lim, const Launch& a, Fn fn) {
   switch (lim) {
-    case LIM_MP: return launch_faces<TENOM_NF, TENOM_K, LIM_MP>(a);
-    case LIM_TVD_MINMOD: return launch_faces<TENOM_NF, TENOM_K, LIM_TVD_MINMOD>(a);
-    case LIM_TVD5: return launch_faces<TENOM_NF, TENOM_K, LIM_TVD5>(a);
+    case LIM_TENO: return fn(std::integral_constant<int, LIM_TENO>{}, std::bool_constant<ADAPT>{}, a);
+    case LIM_MP: return fn(std::integral_constant<int, LIM_MP>{}, std::bool_constant<ADAPT>{}, a);
+    case LIM_TVD_MINMOD: return fn(std::integral_constant<int, LIM_TVD_MINMOD>{}, std::bool_constant<ADAPT>{}, a);
+    case LIM_TVD5: return fn(std::integral_constant<int, LIM_TVD5>{}, std::bool_constant<ADAPT>{}, a);
+    case LIM_VA: return fn(std::integral_constant<int, LIM_VA>{}, std::bool_constant<ADAPT>{}, a);
+    case LIM_MP_MM: return fn(std::integral_constant<int, LIM_MP_MM>{}, std::bool_constant<ADAPT>{}, a);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t TENOM_EXPAND_SWEEP(TENOM_NF, TENOM_K)(int lim, const SweepLaunch& a) {
-  switch (lim) {
-    case LIM_MP: return launch_sweep<TENOM_NF, TENOM_K, LIM_MP>(a);
-    case LIM_TVD_MINMOD: return launch_sweep<TENOM_NF, TENOM_K, LIM_TVD_MINMOD>(a);
-    case LIM_TVD5: return launch_sweep<TENOM_NF, TENOM_K, LIM_TVD5>(a);
-    default: return hipErrorInvalidValue;
-  }
+template <class Launch, class Fn>
+static hipError_t by_scheme(int lim, int adapt, const Launch& a, Fn fn) {
+  if (!adapt) return by_limiter<false>(lim, a, fn);
+  if constexpr (TENOM_K == 8) return by_limiter<true>(lim, a, fn);
+  return hipErrorInvalidValue;  // the adaptive cutoff is defined for K = 8 only
+}
+
+hipError_t TENOM_EXPAND_FACES(TENOM_NF, TENOM_K)(int lim, int adapt, const FacesLaunch& a) {
+  return by_scheme(lim, adapt, a, [](auto L, auto A, const FacesLaunch& x) {
+    return launch_faces<TENOM_NF, TENOM_K, decltype(L)::value, decltype(A)::value>(x);
+  });
+}
+
+hipError_t TENOM_EXPAND_SWEEP(TENOM_NF, TENOM_K)(int lim, int adapt, const SweepLaunch& a) {
+  return by_scheme(lim, adapt, a, [](auto L, auto A, const SweepLaunch& x) {
+    return launch_sweep<TENOM_NF, TENOM_K, decltype(L)::value, decltype(A)::value>(x);
+  });
 }

@@ -92,6 +92,24 @@ def test_rk3_workspace_and_dt_errors(lib):
     assert lib.tenom_workspace_bytes(C.byref(grid(ndim=0)), 6) == 0
 
 
+def test_scheme_and_limiter_ids(lib):
+    g = grid()
+    bad = C.c_void_p(0x2000)
+    # unknown scheme bits, adaptive with K = 6, unknown limiter
+    for scheme, lim in ((6 | 0x200, 1), (6 | 0x100, 1), (8, 9), (8, -1)):
+        rc = lib.tenom_reconstruct_faces(C.byref(g), scheme, lim, 1e-5, 1.4, 0, DUMMY, bad, None, None)
+        assert rc == T.EUNSUPPORTED, (scheme, lim)
+    # classic TENO keeps a candidate only for C_T <= 1/(K-2)
+    # (scheme and limiter arguments are checked before the pointers)
+    rc = lib.tenom_flux_divergence(C.byref(g), 6, T.LIM_TENO, 0.3, 1.4, None, bad, None)
+    assert rc == T.EINVAL and "C_T" in lib.tenom_last_error().decode()
+    # the adaptive scheme ignores C_T, so even a negative one is accepted (NULL U fails later)
+    rc = lib.tenom_flux_divergence(C.byref(g), T.SCHEME_8A, T.LIM_MP, -1.0, 1.4, None, bad, None)
+    assert rc == T.EINVAL and "NULL" in lib.tenom_last_error().decode()
+    assert lib.tenom_workspace_bytes(C.byref(g), T.SCHEME_8A) == lib.tenom_workspace_bytes(C.byref(g), 8)
+    assert lib.tenom_workspace_bytes(C.byref(g), 6 | 0x100) == 0
+
+
 def test_strerror_and_fields(lib):
     for code in (0, -1, -2, -3, -4, -5, -77):
         assert lib.tenom_strerror(code)

@@ -32,6 +32,21 @@ CASES = [
     ("euler3d_mp8_long_z", (80, 8, 16), 1, [0, 0, 0], 8, 1, 1e-7, None),
     ("min_size_6", (6,), 1, [0], 6, 1, 1e-5, None),
     ("min_size_8_trans", (8,), 1, [1], 8, 1, 1e-7, None),
+    # limiter variants (Secs. 3.2.1, 4.2.5, 4.4) and classic renormalised TENO
+    ("euler1d_va6", (300,), 1, [1], 6, 4, 1e-5, None),
+    ("euler2d_va8", (21, 40), 1, [0, 1], 8, 4, 1e-6, None),
+    ("euler1d_mp_m4_b2", (260,), 1, [0], 6, 5, 1e-5, None),
+    ("euler2d_mp_mm_b4", (19, 44), 1, [1, 0], 8, 6, 1e-6, None),
+    ("euler3d_mp_mm_b2", (10, 12, 36), 1, [0, 0, 1], 6, 7, 1e-5, None),
+    ("scalar1d_mp_mm_b1", (150,), 0, [0], 8, 8, 1e-6, [1.0]),
+    ("euler1d_teno6", (300,), 1, [1], 6, 0, 1e-5, None),
+    ("euler3d_teno8", (9, 11, 40), 1, [0, 0, 0], 8, 0, 1e-6, None),
+    # eight points with the adaptive cutoff (TENO8A-M, Sec. 2.4)
+    ("euler1d_8a_mp", (400,), 1, [1], 8 | 0x100, 1, 0.0, None),
+    ("euler2d_8a_tvd5", (25, 48), 1, [0, 0], 8 | 0x100, 3, 0.0, None),
+    ("euler3d_8a_va", (9, 10, 33), 1, [0, 1, 0], 8 | 0x100, 4, 0.0, None),
+    ("euler2d_8a_teno", (20, 36), 1, [1, 1], 8 | 0x100, 0, 0.0, None),
+    ("scalar1d_8a_mp_mm_b2", (257,), 0, [1], 8 | 0x100, 7, 0.0, [-1.3]),
 ]
 IDS = [c[0] for c in CASES]
 
@@ -100,7 +115,7 @@ def rk3_band_cells(orc, U, grid, K, lim, C_T, dt):
         for axis in range(nd):
             _, _, bd = orc.reconstruct_faces(S, grid, K, lim, C_T, GAMMA, axis)
             excl |= faces_to_cells(band_faces(bd), nd - 1 - axis, grid["n"][axis], grid["bc"][axis] == 0,
-                                   3 * K // 2)
+                                   3 * (K & 0xFF) // 2)
     return excl
 
 
@@ -145,6 +160,31 @@ def test_cutoff_extremes(T, orc, C_T, expect, K):
         assert np.all(flg == (full if expect == "all" else 0))
         assert np.array_equal(flg, flo)
         assert_close_fields(to_host(Fg), Fo, what=f"C_T={C_T}")
+
+
+@pytest.mark.parametrize("scheme", [6, 8, 8 | 0x100])
+def test_flags_do_not_depend_on_the_limiter(T, orc, scheme):
+    """The cutoff is taken before any limiter (Sec. 3.1), so every limiter
+    kind gives the same flags on the same input.  Transmissive axes put runs
+    of equal ghost values in the boundary stencils: their differences, and
+    so beta_k, must be exactly zero in every kernel instantiation."""
+    grid = dict(ndim=2, n=[37, 23], dx=[0.05, 0.07], bc=[1, 1], system=1)
+    U = W.random_euler_state((23, 37), seed=211, kind="mixed")
+    C_T = 1e-6
+    Ud = to_dev(U)
+    for axis in range(2):
+        print(f"[flags_vs_limiter] scheme={scheme} axis={axis}", flush=True)
+        _, flo, bdo = orc.reconstruct_faces(U, grid, scheme, 1, C_T, GAMMA, axis)
+        band = band_faces(bdo)
+        ref = None
+        for lim in range(9):
+            _, flg = T.reconstruct_faces(Ud, grid, scheme, lim, C_T, GAMMA, axis, return_flags=True)
+            flg = to_host(flg)
+            if ref is None:
+                ref = flg
+            assert np.array_equal(flg, ref), f"limiter {lim}: flags differ from limiter 0"
+        mism = (ref != flo) & ~band[None, None]
+        assert not mism.any(), f"{int(mism.sum())} flag mismatches outside the band"
 
 
 def test_constant_state_is_steady(T):
