@@ -14,6 +14,16 @@ Prints one JSON line.  Inputs are resident in HBM before timing starts.
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
                     [--calibrate-copy]   (adds a plain 1 GiB device copy,
                                           the HBM-counter scale reference)
+    python bench.py --variants [--steps K]
+        one JSON line with the cost of the same RK3 step for every scheme
+        (TENO6, TENO8, TENO8A) and limiter, relative to classic TENO of the
+        same scheme, in the manner of the paper's Table 2
+    python bench.py --batched [--batch-steps 100] [--per-problem-steps 3]
+        one JSON line for the batched path: 4096 independent 1D Euler
+        Riemann problems, n log-uniform in [256, 16384] (15.9 M cells),
+        TENO8-M-MP, C_T = 1e-7, CFL 0.4 with each problem's own step, 100
+        SSP-RK3 steps as one replay of a captured graph after the tile
+        autotuner, against one launch per problem
 """
 from __future__ import annotations
 
@@ -60,8 +70,10 @@ BYTES_PER_CELL_STEP = 320
 # by 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB device copy reads
 # as).  They describe the kernels built from the sources whose digest is
 # TRAFFIC_SOURCE_DIGEST and are reported as null for any other build.
-TRAFFIC_SOURCE_DIGEST = "dac703a37bf04cb3cea84ee29149123ff9da5a6314c1926f65f68df941227ea7"
-MEASURED_TRAFFIC = {"sweep_x": 1.3425e9, "sweep_y": 2.0765e9, "sweep_z": 2.5239e9}
+TRAFFIC_SOURCE_DIGEST = "0a31da1c1d5f25a08d0b0087367db6c3d10953ecc5aa0a7ba656bbd4d2442563"
+MEASURED_TRAFFIC = {"sweep_x": 1.3425e9, "sweep_y": 2.0765e9, "sweep_z": 2.5239e9,
+                    # batched sweep, 4096 problems, averaged over the stages
+                    "batch_sweep": 1.2623e9}
 
 
 def kernel_source_digest() -> str:
@@ -86,7 +98,197 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--variants", action="store_true")
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--per-problem-steps", type=int, default=3)
     return ap.parse_args()
+
+
+# Algorithmic FP64 operations per 1D Euler face vector, K = 8, MP limiter
+# (same counting rules as FLOPS_PER_FACE_VECTOR):
+#   cell primitives, flux and Roe inputs, once per cell     30
+#   Rusanov alpha (max over 8 cells)                         8
+#   Roe average and eigenvector constants                   23
+#   projection of 8 U and 8 F vectors on L                 240
+#   Rusanov split of 3 fields x 8 cells                     72
+#   TENO-M, 6 scalar reconstructions x 297               1782
+#   back-projection with R                                  20
+#   divergence and stage update, once per cell              18
+FLOPS_PER_FACE_VECTOR_1D_K8 = 2193
+
+
+def run_batched(args):
+    """The batched workload; returns the JSON object."""
+    import numpy as np
+    import torch
+
+    import paper_2010_13289_amd as T
+    import workloads as W
+    sizes = W.batched_riemann_sizes()
+    parts, dx = [], []
+    for p, n in enumerate(sizes):
+        left, right = W.riemann_states(p)
+        Up, h = W.riemann_problem(int(n), left, right, gamma=GAMMA)
+        parts.append(Up)
+        dx.append(h)
+    U_host = np.concatenate(parts, axis=1)
+    plan = T.BatchPlan(sizes, dx, T.BC_TRANSMISSIVE)
+    U0 = torch.from_numpy(U_host).to("cuda")
+    U = U0.clone()
+    scheme, lim, ct = 8, T.LIM_MP, 1e-7
+    best, tile_ms = plan.autotune(U, scheme, lim, ct, GAMMA, CFL, steps=2)
+    steps = args.batch_steps
+    faces_per_stage = plan.total + plan.count  # n + 1 faces per problem
+    faces = 3 * steps * faces_per_stage
+    # capture and one untimed replay, then the timed replay from the same state
+    plan.rk3_graph(U, scheme, lim, ct, GAMMA, CFL, steps=steps)
+    torch.cuda.synchronize()
+    U.copy_(U0)
+    plan.reset_times()
+    torch.cuda.synchronize()
+    T.profile_read()
+    T.profile_enable(True)
+    t0 = time.perf_counter()
+    plan.rk3_graph(U, scheme, lim, ct, GAMMA, CFL, steps=steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    T.profile_enable(False)
+    graph_ms = T.profile_read()["batch_graph"][1]
+    ok = bool(torch.isfinite(U).all().item())
+    # per-kernel averages from eager steps (kernels inside a graph are not
+    # bracketed one by one)
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    T.profile_enable(True)
+    plan.rk3(U, scheme, lim, ct, GAMMA, CFL, steps=5)
+    torch.cuda.synchronize()
+    T.profile_enable(False)
+    prof = T.profile_read()
+    sweep_n, sweep_ms = prof["batch_sweep"]
+    dt_n, dt_ms = prof["batch_dt"]
+    avg_s = sweep_ms / 1e3 / max(sweep_n, 1)
+    achieved = FLOPS_PER_FACE_VECTOR_1D_K8 * faces_per_stage / avg_s / 1e12
+    sec_per_step = graph_ms / 1e3 / steps
+    # one launch per problem: the same kernels with first = p, count = 1
+    pp = args.per_problem_steps
+    per_problem = None
+    if pp > 0:
+        U.copy_(U0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0 = time.perf_counter()
+        e0.record()
+        for p in range(plan.count):
+            plan.rk3(U, scheme, lim, ct, GAMMA, CFL, steps=pp, first=p, count=1)
+        e1.record()
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        pp_wall = (p1 - p0) / pp
+        per_problem = {
+            "launches_per_step": 4 * plan.count,
+            "ms_per_step_wall": pp_wall * 1e3,
+            "ms_per_step_gpu": e0.elapsed_time(e1) / pp,
+            "steps_timed": pp,
+            "face_reconstructions_per_s": 3 * faces_per_stage / pp_wall,
+            "batched_speedup": pp_wall / sec_per_step,
+        }
+    value = faces / (graph_ms / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "face-reconstructions/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 1,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched 1D Euler: 4096 seeded Riemann problems, n log-uniform in [256, 16384], "
+                        "TENO8-M-MP, C_T=1e-7, gamma=1.4, CFL 0.4 per problem, 100 SSP-RK3 steps in one "
+                        "replay of a captured HIP graph",
+            "problems": plan.count,
+            "cells": plan.total,
+            "face_vectors_per_step": 3 * faces_per_stage,
+            "tile": {"id": best, "threads": T.batch_tile_shape(best)[0],
+                     "faces_per_thread": T.batch_tile_shape(best)[1]},
+            "autotune_ms_per_step": tile_ms,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "batch_sweep",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": (MEASURED_TRAFFIC["batch_sweep"] if kernel_source_digest() == TRAFFIC_SOURCE_DIGEST
+                        else None),
+            "avg_launch_ms": avg_s * 1e3,
+            "flops_per_launch": FLOPS_PER_FACE_VECTOR_1D_K8 * faces_per_stage,
+        },
+        "graph_wall_ms": (t1 - t0) * 1e3,
+        "step_size_kernel_avg_ms": dt_ms / max(dt_n, 1),
+        "per_problem_launches": per_problem,
+        "state_finite": ok,
+    }
+    plan.close()
+    return out
+
+
+# (name, scheme, limiter, C_T) of the variant report; classic TENO first in
+# each group, the reference of the ratios.  The adaptive scheme ignores C_T.
+VARIANTS = [
+    ("TENO6", 6, 0, 1e-5), ("TENO6-M-MP", 6, 1, 1e-5), ("TENO6-M-TVD5", 6, 3, 1e-5),
+    ("TENO6-M-VA", 6, 4, 1e-5), ("TENO6-M-TVD(minmod)", 6, 2, 1e-5), ("TENO6-M-MP(M4,b2)", 6, 5, 1e-5),
+    ("TENO6-M-MP(MM,b4)", 6, 6, 1e-5), ("TENO6-M-MP(MM,b2)", 6, 7, 1e-5), ("TENO6-M-MP(MM,b1)", 6, 8, 1e-5),
+    ("TENO8", 8, 0, 1e-7), ("TENO8-M-MP", 8, 1, 1e-7), ("TENO8-M-TVD5", 8, 3, 1e-7), ("TENO8-M-VA", 8, 4, 1e-7),
+    ("TENO8A", 8 | 0x100, 0, 0.0), ("TENO8A-M-MP", 8 | 0x100, 1, 0.0), ("TENO8A-M-TVD5", 8 | 0x100, 3, 0.0),
+    ("TENO8A-M-VA", 8 | 0x100, 4, 0.0),
+]
+
+
+def run_variants(T, U0, grid, n, steps, warmup):
+    """Time one RK3 step of every variant from the same initial state."""
+    import torch
+    rows = []
+    ref = {}
+    for name, scheme, lim, ct in VARIANTS:
+        U = U0.clone()
+        ws = T.Workspace(grid, scheme, U.device)
+
+        def step():
+            rate = T.max_wave_speed(U, grid, GAMMA)
+            T.rk3_step(U, grid, scheme, lim, ct, GAMMA, CFL / rate, workspace=ws)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        T.profile_read()
+        T.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        T.profile_enable(False)
+        prof = T.profile_read()
+        ms = (t1 - t0) / steps * 1e3
+        group = name.split("-")[0]
+        ref.setdefault(group, ms)
+        rows.append({
+            "variant": name, "scheme": scheme, "limiter": lim, "C_T": ct, "ms_per_step": ms,
+            "face_vectors_per_s": 9 * n ** 3 / (ms / 1e3),
+            "ratio_vs_classic": ms / ref[group],
+            "sweep_avg_ms": {k: prof[k][1] / max(prof[k][0], 1) for k in ("sweep_x", "sweep_y", "sweep_z")},
+            "state_finite": T.check_finite(U, grid),
+        })
+        print(f"# {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        del ws, U
+    return rows
 
 
 def cpu_baseline(U, grid, seconds):
@@ -134,10 +336,24 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.batched:
+        print(json.dumps(run_batched(args)), flush=True)
+        return
     n = args.n
     U_host, dx = W.tgv_3d(n, gamma=GAMMA)
     grid = dict(ndim=3, n=[n, n, n], dx=[dx] * 3, bc=[0, 0, 0], system=1)
     U0 = torch.from_numpy(U_host).to(dev)
+    if args.variants:
+        rows = run_variants(T, U0, grid, n, args.steps, args.warmup)
+        print(json.dumps({
+            "report": "variants", "unit": "ms per SSP-RK3 step", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"3D Euler {n}^3 periodic TGV + density jump + seeded perturbations, "
+                                   "gamma=1.4, CFL 0.4, one SSP-RK3 step per variant from the same state",
+                       "grid": [n, n, n]},
+            "rows": rows,
+        }), flush=True)
+        return
     U = U0.clone()
     ws = T.Workspace(grid, SCHEME, dev)
 

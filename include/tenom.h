@@ -173,6 +173,90 @@ int tenom_max_wave_speed(const tenom_grid* grid, double gamma, const double* U, 
  * Synchronises `stream`. */
 int tenom_check_finite(const tenom_grid* grid, const double* U, void* stream);
 
+/* ---- batched independent 1D problems ------------------------------------ */
+/*
+ * Many independent 1D Euler problems of uneven size (the shock tubes of
+ * Sec. 4.2, one per problem) advanced together: each problem p has n[p]
+ * cells of size dx[p], the same boundary rule at both of its ends, and its
+ * own SSP-RK3 step dt_p = cfl / max_cells (|u| + c) / dx[p], computed on the
+ * device at the start of every step from the problem's current state.
+ *
+ * State layout: one device array [3][total] (rho, rho*u, E), the problems
+ * packed end to end in order: problem p occupies cells
+ * off[p] .. off[p] + n[p] - 1 of every field, off[p] = n[0] + ... + n[p-1],
+ * and total = off[count] (tenom_batch_cells).
+ *
+ * The plan holds everything the calls need on the device: the problem
+ * offsets, 1/dx, each problem's last dt and its clock (the sum of its
+ * steps), two stage states of 3 * total doubles (the RK3 intermediates), a
+ * segment table per tile shape, and the captured graph.  A plan belongs to
+ * the device that was current at tenom_batch_create; every call needs that
+ * device current.  Calls on one plan must not run concurrently.
+ */
+typedef struct tenom_batch_plan tenom_batch_plan;
+
+/* Tile shapes of the batched sweep: a workgroup of `threads` threads
+ * computes threads * faces_per_thread faces of one problem. */
+#define TENOM_BATCH_TILES 6
+int tenom_batch_tile_shape(int tile, int* threads, int* faces_per_thread);
+
+/*
+ * Create a plan for `count` problems (count >= 0; 0 makes every call a
+ * no-op).  n, dx: HOST arrays of count entries, n[p] >= 6, dx[p] > 0.
+ * bc: TENOM_BC_PERIODIC or TENOM_BC_TRANSMISSIVE for every problem.
+ * Allocates the plan's device memory (about 48 * total bytes plus small
+ * tables); clocks start at 0; the tile is 3 until set or autotuned.
+ * Errors: EINVAL for bad arguments (no allocation), EHIP if an allocation
+ * fails.
+ */
+int tenom_batch_create(int count, const int64_t* n, const double* dx, int bc, tenom_batch_plan** plan);
+/* Synchronise the device and free the plan (NULL is a no-op). */
+int tenom_batch_destroy(tenom_batch_plan* plan);
+/* Total cells of the batch (the field pitch of U), -1 for NULL. */
+int64_t tenom_batch_cells(const tenom_batch_plan* plan);
+/* Select the tile shape of later calls (0 .. TENOM_BATCH_TILES-1). */
+int tenom_batch_set_tile(tenom_batch_plan* plan, int tile);
+int tenom_batch_get_tile(const tenom_batch_plan* plan);
+
+/*
+ * Enqueue `steps` SSP-RK3 steps (Sec. 4) of problems first .. first+count-1
+ * on `stream`, in place on U (device, [3][total]).  Per step: one kernel for
+ * the step sizes of the selected problems, then three stage sweeps, each
+ * one launch over all selected problems (reconstruction as in
+ * tenom_reconstruct_faces, divergence and the stage update fused).  Other
+ * problems' cells are not touched.  No allocation, no synchronisation.
+ * Every problem needs n >= K.  Euler system only (gamma > 1).
+ */
+int tenom_batch_rk3(tenom_batch_plan* plan, int scheme, int limiter, double C_T, double gamma, double cfl, int steps,
+                    int first, int count, double* U, void* stream);
+
+/*
+ * The same for all problems as one HIP graph launch on `stream`: the first
+ * call captures the `steps` steps (4 * steps kernels) into a graph the
+ * plan keeps; later calls with the same arguments, U and tile replay it.
+ * Other arguments recapture.  Equal in every bit to tenom_batch_rk3.
+ */
+int tenom_batch_rk3_graph(tenom_batch_plan* plan, int scheme, int limiter, double C_T, double gamma, double cfl,
+                          int steps, double* U, void* stream);
+
+/*
+ * Autotuner of the tile shape: time `steps` steps (after one untimed step)
+ * of every tile on a copy of U, for this scheme and limiter, select the
+ * fastest for later calls and return it in *best (nullable).
+ * ms_per_step: nullable HOST array of TENOM_BATCH_TILES entries.  U and the
+ * plan's clocks are left as they were.  Allocates one temporary state copy
+ * and synchronises `stream`.  Every tile gives the same bits, so the choice
+ * changes only the speed.
+ */
+int tenom_batch_autotune(tenom_batch_plan* plan, int scheme, int limiter, double C_T, double gamma, double cfl,
+                         const double* U, int steps, float* ms_per_step, int* best, void* stream);
+
+/* Each problem's clock (sum of its steps) and last step into HOST arrays of
+ * count entries (either nullable); synchronises `stream`. */
+int tenom_batch_times(const tenom_batch_plan* plan, double* t, double* dt, void* stream);
+/* Set every clock and last step to 0 (enqueued on `stream`). */
+int tenom_batch_reset_times(tenom_batch_plan* plan, void* stream);
+
 /* ---- diagnostics -------------------------------------------------------- */
 
 /* Static text for a return code. */
@@ -188,9 +272,11 @@ int tenom_version(void);
  * synchronises those events and returns, per kernel kind, the number of
  * launches and their summed duration in milliseconds since the last reset.
  * Kinds: 0 face fluxes (reconstruct_faces), 1 x-sweep, 2 y-sweep,
- * 3 z-sweep.  At most 4096 launches are recorded between reads.
+ * 3 z-sweep, 4 batched sweep, 5 batched step size, 6 one replay of a batched
+ * graph (kernels inside a graph are not bracketed one by one).  At most 4096
+ * launches are recorded between reads.
  */
-#define TENOM_KERNEL_KINDS 4
+#define TENOM_KERNEL_KINDS 7
 int tenom_profile_enable(int on);
 int tenom_profile_read(int64_t* counts, double* total_ms, int nkinds);
 

@@ -25,12 +25,16 @@ SCHEME_ADAPTIVE = 0x100
 SCHEME_8A = SCHEME_8 | SCHEME_ADAPTIVE   # eight points, adaptive cutoff (TENO8A)
 LIM_TENO, LIM_MP, LIM_TVD_MINMOD, LIM_TVD5, LIM_VA = 0, 1, 2, 3, 4
 LIM_MP_M4_B2, LIM_MP_MM_B4, LIM_MP_MM_B2, LIM_MP_MM_B1 = 5, 6, 7, 8
-KERNEL_KINDS = ("faces", "sweep_x", "sweep_y", "sweep_z")
+KERNEL_KINDS = ("faces", "sweep_x", "sweep_y", "sweep_z", "batch_sweep", "batch_dt", "batch_graph")
+BATCH_TILES = 6
 
 SYMBOLS = (
     "tenom_num_fields", "tenom_reconstruct_faces", "tenom_flux_divergence", "tenom_rk3_step",
     "tenom_workspace_bytes", "tenom_max_wave_speed", "tenom_check_finite", "tenom_strerror",
     "tenom_last_error", "tenom_version", "tenom_profile_enable", "tenom_profile_read",
+    "tenom_batch_tile_shape", "tenom_batch_create", "tenom_batch_destroy", "tenom_batch_cells",
+    "tenom_batch_set_tile", "tenom_batch_get_tile", "tenom_batch_rk3", "tenom_batch_rk3_graph",
+    "tenom_batch_autotune", "tenom_batch_times", "tenom_batch_reset_times",
 )
 
 
@@ -118,6 +122,20 @@ def lib() -> C.CDLL:
         L.tenom_last_error.restype = C.c_char_p
         L.tenom_profile_enable.argtypes = [C.c_int]
         L.tenom_profile_read.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int]
+        ip = C.c_int
+        L.tenom_batch_tile_shape.argtypes = [ip, C.POINTER(ip), C.POINTER(ip)]
+        L.tenom_batch_create.argtypes = [ip, C.POINTER(C.c_int64), C.POINTER(C.c_double), ip, C.POINTER(vp)]
+        L.tenom_batch_destroy.argtypes = [vp]
+        L.tenom_batch_cells.argtypes = [vp]
+        L.tenom_batch_cells.restype = C.c_int64
+        L.tenom_batch_set_tile.argtypes = [vp, ip]
+        L.tenom_batch_get_tile.argtypes = [vp]
+        L.tenom_batch_rk3.argtypes = [vp, ip, ip, dp, dp, dp, ip, ip, ip, vp, vp]
+        L.tenom_batch_rk3_graph.argtypes = [vp, ip, ip, dp, dp, dp, ip, vp, vp]
+        L.tenom_batch_autotune.argtypes = [vp, ip, ip, dp, dp, dp, vp, ip, C.POINTER(C.c_float),
+                                           C.POINTER(ip), vp]
+        L.tenom_batch_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
+        L.tenom_batch_reset_times.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -248,3 +266,96 @@ def profile_read() -> dict:
     ms = (C.c_double * n)()
     _check(lib().tenom_profile_read(cnt, ms, n))
     return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+# ---------------------------------------------------------------------------
+# batched independent 1D Euler problems
+# ---------------------------------------------------------------------------
+
+def batch_tile_shape(tile: int) -> tuple[int, int]:
+    """(threads per workgroup, faces per thread) of a batched tile shape."""
+    t, f = C.c_int(), C.c_int()
+    _check(lib().tenom_batch_tile_shape(int(tile), C.byref(t), C.byref(f)))
+    return t.value, f.value
+
+
+class BatchPlan:
+    """Plan of a batch of independent 1D Euler problems (tenom_batch_*).
+
+    sizes[p] cells of size dx[p] per problem, one boundary rule for all.
+    The state is a float64 tensor [3, total] with the problems packed end to
+    end (``offsets`` gives each problem's first cell)."""
+
+    def __init__(self, sizes, dx, bc: int = BC_TRANSMISSIVE):
+        import numpy as np
+        n = np.ascontiguousarray(sizes, dtype=np.int64)
+        d = np.ascontiguousarray(dx, dtype=np.float64)
+        if n.ndim != 1 or d.shape != n.shape:
+            raise ValueError("sizes and dx must be 1D arrays of equal length")
+        self.count = int(n.size)
+        self.sizes = n
+        self.offsets = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+        self._h = C.c_void_p()
+        _check(lib().tenom_batch_create(self.count, n.ctypes.data_as(C.POINTER(C.c_int64)),
+                                        d.ctypes.data_as(C.POINTER(C.c_double)), int(bc), C.byref(self._h)))
+        self.total = int(lib().tenom_batch_cells(self._h))
+
+    def close(self):
+        if self._h:
+            _check(lib().tenom_batch_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _state(self, U):
+        import torch
+        if not isinstance(U, torch.Tensor) or U.dtype != torch.float64 or not U.is_cuda or not U.is_contiguous():
+            raise ValueError("U must be a contiguous float64 tensor on a HIP device")
+        if tuple(U.shape) != (3, self.total):
+            raise ValueError(f"U has shape {tuple(U.shape)}, expected (3, {self.total})")
+        return C.c_void_p(U.data_ptr())
+
+    @property
+    def tile(self) -> int:
+        return int(lib().tenom_batch_get_tile(self._h))
+
+    @tile.setter
+    def tile(self, t: int):
+        _check(lib().tenom_batch_set_tile(self._h, int(t)))
+
+    def rk3(self, U, scheme, limiter, C_T, gamma, cfl, steps=1, first=0, count=None, stream=None):
+        """Enqueue `steps` RK3 steps of problems [first, first + count)."""
+        count = self.count - first if count is None else count
+        _check(lib().tenom_batch_rk3(self._h, scheme, limiter, C_T, gamma, cfl, int(steps), int(first), int(count),
+                                     self._state(U), _stream(stream)))
+        return U
+
+    def rk3_graph(self, U, scheme, limiter, C_T, gamma, cfl, steps=1, stream=None):
+        """`steps` RK3 steps of every problem as one captured-graph launch."""
+        _check(lib().tenom_batch_rk3_graph(self._h, scheme, limiter, C_T, gamma, cfl, int(steps),
+                                           self._state(U), _stream(stream)))
+        return U
+
+    def autotune(self, U, scheme, limiter, C_T, gamma, cfl, steps=2, stream=None):
+        """Time every tile shape; select the fastest.  Returns (tile, ms/step per tile)."""
+        ms = (C.c_float * BATCH_TILES)()
+        best = C.c_int()
+        _check(lib().tenom_batch_autotune(self._h, scheme, limiter, C_T, gamma, cfl, self._state(U), int(steps),
+                                          ms, C.byref(best), _stream(stream)))
+        return best.value, [float(v) for v in ms]
+
+    def times(self, stream=None):
+        """(clock, last step) of every problem as numpy arrays (synchronises)."""
+        import numpy as np
+        t = np.zeros(self.count)
+        dt = np.zeros(self.count)
+        _check(lib().tenom_batch_times(self._h, t.ctypes.data_as(C.POINTER(C.c_double)),
+                                       dt.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+        return t, dt
+
+    def reset_times(self, stream=None):
+        _check(lib().tenom_batch_reset_times(self._h, _stream(stream)))

@@ -1,8 +1,9 @@
 """Build libtenom.so (HIP, gfx950) in-tree.
 
 Steps: regenerate csrc/teno_tables.h from gen_tables.py, compile the eight
-instantiation units (fields x K) and the C-ABI layer in parallel with hipcc,
-link them into paper_2010_13289_amd/libtenom.so.
+instantiation units (fields x K), the six batched-path units (one per tile
+shape) and the two C-ABI sources in parallel with hipcc, link them into
+paper_2010_13289_amd/libtenom.so.
 
     python -m paper_2010_13289_amd.build [--verbose]
 """
@@ -28,9 +29,14 @@ HIPCC_FLAGS = [
     "-Wno-unused-result",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: every fused multiply-add is written in the
+    # source, so each kernel instantiation (and each batched tile shape)
+    # rounds the same way and gives the same bits
+    "-ffp-contract=off",
 ]
 
 UNITS = [(nf, k) for nf in (1, 3, 4, 5) for k in (6, 8)]
+BATCH_TILES = 6  # tile shapes of the batched path (kTiles in teno_batch.h)
 
 
 def _hipcc() -> str:
@@ -75,9 +81,15 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         objs.append(obj)
         cmds.append([hipcc, *HIPCC_FLAGS, f"-DTENOM_NF={nf}", f"-DTENOM_K={k}", "-c",
                      os.path.join(CSRC, "tenom_inst.hip"), "-o", obj])
-    obj = os.path.join(BUILD, "tenom_abi.o")
-    objs.append(obj)
-    cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, "tenom_abi.hip"), "-o", obj])
+    for t in range(BATCH_TILES):
+        obj = os.path.join(BUILD, f"batch_tile{t}.o")
+        objs.append(obj)
+        cmds.append([hipcc, *HIPCC_FLAGS, f"-DTENOM_TILE={t}", "-c",
+                     os.path.join(CSRC, "tenom_batch_inst.hip"), "-o", obj])
+    for src in ("tenom_abi.hip", "tenom_batch.hip"):
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        objs.append(obj)
+        cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
     if jobs is None:
         jobs = int(os.environ.get("MAX_JOBS", "0") or 0) or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

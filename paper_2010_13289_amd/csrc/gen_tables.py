@@ -140,18 +140,22 @@ def lit(x: Fr) -> str:
 
 
 def linear_form(coefs, names):
+    """sum_j coefs[j] * names[j] as an explicit chain of fused multiply-adds
+    (the library is compiled without contraction, so the rounding of every
+    step is the one written here)."""
     terms = [(c, n) for c, n in zip(coefs, names) if c != 0]
     if not terms:
         return "0.0"
-    out = []
-    for c, n in terms:
+    c, n = terms[0]
+    expr = n if c == 1 else (f"-{n}" if c == -1 else f"{lit(c)} * {n}")
+    for c, n in terms[1:]:
         if c == 1:
-            out.append(f"{n}")
+            expr = f"{expr} + {n}"
         elif c == -1:
-            out.append(f"-{n}")
+            expr = f"{expr} - {n}"
         else:
-            out.append(f"{lit(c)} * {n}")
-    return " + ".join(out).replace("+ -", "- ")
+            expr = f"fma({lit(c)}, {n}, {expr})"
+    return expr
 
 
 def emit(K: int) -> str:

@@ -114,7 +114,7 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
   // smoothness indicators and the global tau_K (Eqs. measureTENO, taukTENO)
   double beta[NK], betaK;
   T::betas(D, beta, betaK);
-  const double tau = fabs(betaK - (beta[1] + beta[2] + 4.0 * beta[0]) * (1.0 / 6.0));
+  const double tau = fabs(fma(fma(4.0, beta[0], beta[1] + beta[2]), -1.0 / 6.0, betaK));
 
   // gamma_k and the cutoff: chi_k = gamma_k / sum < C_T  <=>  gamma_k < C_T sum
   double g[NK];
@@ -123,8 +123,9 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
   for (int k = 0; k < NK; ++k) {
     const double s = fma(tau, rcp1(beta[k] + kEps2x), 1.0);
     const double s2 = s * s;
-    g[k] = s2 * s2 * s2;
-    sum += g[k];
+    const double s4 = s2 * s2;
+    g[k] = s4 * s2;
+    sum = fma(s4, s2, sum);  // the sum takes gamma_k unrounded
   }
   const double thr = C_T * sum;
 
@@ -140,15 +141,15 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
     const double d_ip1 = D[C0 + 1] - D[C0];
     double dR, dL;
     if constexpr (LIM == LIM_MP) {
-      dR = minmod4(4.0 * d_i - d_ip1, 4.0 * d_ip1 - d_i, d_i, d_ip1);
-      dL = minmod4(4.0 * d_im1 - d_i, 4.0 * d_i - d_im1, d_im1, d_i);
+      dR = minmod4(fma(4.0, d_i, -d_ip1), fma(4.0, d_ip1, -d_i), d_i, d_ip1);
+      dL = minmod4(fma(4.0, d_im1, -d_i), fma(4.0, d_i, -d_im1), d_im1, d_i);
     } else {
       dR = minmod2(d_i, d_ip1);
       dL = minmod2(d_im1, d_i);
     }
     // Eqs. upper_limiter, median_value, large_curvature (alpha 1.25)
     const double ul = 1.25 * dm;
-    const double md = 0.5 * dp - 0.5 * dR;
+    const double md = fma(0.5, dp, -0.5 * dR);
     const double lc = fma(tp.mp_beta3, dL, 0.5 * dm);
     // Eq. value_min_max; 0 (= f_i) lies in both brackets, so lo <= 0 <= hi
     lo = fmax(fmin(fmin(0.0, dp), md), fmin(fmin(0.0, ul), lc));
@@ -158,15 +159,18 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
   } else if constexpr (LIM == LIM_TVD5) {
     // Eqs. high order TVD, TVDhighorder2, TVDbeta multiplied through by
     // delta^- (division-free; equal wherever the slope ratios exist)
-    const double B = (-2.0 * D[C0 - 2] + 11.0 * dm + 24.0 * dp - 3.0 * D[C0 + 1]) * (1.0 / 30.0);
+    const double B = fma(-3.0, D[C0 + 1], fma(24.0, dp, fma(11.0, dm, -2.0 * D[C0 - 2]))) * (1.0 / 30.0);
     const double up = fmax(0.0, fmin(fmin(2.0 * dm, 2.0 * dp), B));
     const double dn = fmin(0.0, fmax(fmax(2.0 * dm, 2.0 * dp), B));
     ftvd = 0.5 * (dm > 0.0 ? up : (dm < 0.0 ? dn : 0.0));
   } else if constexpr (LIM == LIM_VA) {
     // Eqs. van_Albada_limiter, slop_ratio, vAflux with kappa = 1/3:
-    // phi = 2 r/(r^2 + 1) = 2 d+ d- / (d+^2 + d-^2), 0 when both vanish
-    const double den = fma(dp, dp, dm * dm);
-    const double phi = den > 0.0 ? 2.0 * dp * dm * rcp(den) : 0.0;
+    // phi = 2 r/(r^2 + 1) = 2 d+ d- / (d+^2 + d-^2), 0 when both vanish.
+    // Branch-free: the denominator is raised to the smallest normal, which
+    // changes nothing unless |d+|, |d-| < 1e-154, and gives 0 * finite = 0
+    // when both differences vanish.
+    const double den = fmax(fma(dp, dp, dm * dm), 2.2250738585072014e-308);
+    const double phi = 2.0 * dp * dm * rcp(den);
     const double kp = phi * (1.0 / 3.0);
     ftvd = 0.25 * phi * fma(1.0 - kp, dm, (1.0 + kp) * dp);
   }
@@ -182,7 +186,7 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
       den = smooth ? den + T::d(k) : den;
       if constexpr (FLAGS) bits |= (smooth ? 1u : 0u) << k;
     }
-    return v[C0] + num * rcp(den);
+    return fma(num, rcp(den), v[C0]);
   } else {
     // assembly with the optimal weights, no renormalisation (Eq. reconstuction)
     double acc = 0.0;

@@ -168,8 +168,16 @@ struct StagedCells {
   __device__ __forceinline__ double value(int m) const { return at(0, c0 + m); }
 };
 
+// Waves per SIMD the row sweep is compiled for: three where the face fits
+// in 168 VGPRs without spilling (six points), else what the registers allow.
+template <int NF, int K>
+struct RowOccupancy {
+  static constexpr int WAVES = (K == 6) ? 3 : 1;
+};
+
 template <int NF, int K, int LIM, bool ADAPT>
-__global__ __launch_bounds__(256) void k_sweep_row(SweepParams<NF> p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowOccupancy<NF, K>::WAVES)))
+void k_sweep_row(SweepParams<NF> p) {
   constexpr int NC = 256 + K - 1;  // staged cells per segment
   constexpr int NE = RowStage<NF>::NE;
   __shared__ double stage[NE * NC];

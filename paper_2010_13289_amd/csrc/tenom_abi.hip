@@ -13,25 +13,14 @@
 #include <vector>
 
 #include "../../include/tenom.h"
+#include "abi_common.h"
 #include "dispatch.h"
 
 using namespace tenom;
 
 namespace {
 
-thread_local char g_err[512] = "";
-
-int fail(int code, const char* fmt, ...) {
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(g_err, sizeof(g_err), fmt, ap);
-  va_end(ap);
-  return code;
-}
-
-int hip_fail(hipError_t e, const char* what) {
-  return fail(TENOM_EHIP, "%s: %s", what, hipGetErrorString(e));
-}
+using namespace tenom::abi;
 
 int nfields(const tenom_grid* g) {
   if (!g) return 0;
@@ -68,33 +57,6 @@ int check_grid(const tenom_grid* g, int K) {
     if (cells > (1L << 31) - 1) return fail(TENOM_EINVAL, "grid has more than 2^31-1 cells");
   }
   return TENOM_OK;
-}
-
-// scheme -> K (0 if invalid) and the adaptive-cutoff flag
-int scheme_K(int scheme, bool* adaptive) {
-  const int K = scheme & 0xff;
-  *adaptive = (scheme & TENOM_SCHEME_ADAPTIVE) != 0;
-  if (scheme & ~(0xff | TENOM_SCHEME_ADAPTIVE)) return 0;
-  if (K != 6 && K != 8) return 0;
-  if (*adaptive && K != 8) return 0;
-  return K;
-}
-
-// limiter ID -> kernel limiter kind and the beta of Eq. large_curvature
-bool limiter_kind(int id, int* kind, double* beta) {
-  *beta = 4.0;
-  switch (id) {
-    case TENOM_LIM_TENO: *kind = LIM_TENO; return true;
-    case TENOM_LIM_MP: *kind = LIM_MP; return true;
-    case TENOM_LIM_TVD_MINMOD: *kind = LIM_TVD_MINMOD; return true;
-    case TENOM_LIM_TVD5: *kind = LIM_TVD5; return true;
-    case TENOM_LIM_VA: *kind = LIM_VA; return true;
-    case TENOM_LIM_MP_M4_B2: *kind = LIM_MP; *beta = 2.0; return true;
-    case TENOM_LIM_MP_MM_B4: *kind = LIM_MP_MM; return true;
-    case TENOM_LIM_MP_MM_B2: *kind = LIM_MP_MM; *beta = 2.0; return true;
-    case TENOM_LIM_MP_MM_B1: *kind = LIM_MP_MM; *beta = 1.0; return true;
-    default: return false;
-  }
 }
 
 int check_scheme(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma) {
@@ -163,51 +125,6 @@ bool pick(int nf, int K, FacesFn* f, SweepFn* s) {
 #undef TENOM_CASE
   return false;
 }
-
-// ---------------------------------------------------------------------------
-// kernel timing
-// ---------------------------------------------------------------------------
-struct ProfRec {
-  int kind;
-  hipEvent_t a, b;
-};
-
-std::mutex g_prof_mu;
-bool g_prof_on = false;
-std::vector<hipEvent_t> g_event_pool;
-std::vector<ProfRec> g_prof_recs;
-constexpr size_t kMaxProf = 4096;
-
-hipEvent_t pool_event() {
-  if (!g_event_pool.empty()) {
-    hipEvent_t e = g_event_pool.back();
-    g_event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-struct ProfScope {
-  int kind;
-  hipStream_t s;
-  hipEvent_t a = nullptr, b = nullptr;
-  bool on = false;
-  ProfScope(int k, hipStream_t st) : kind(k), s(st) {
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof_on || g_prof_recs.size() >= kMaxProf) return;
-    a = pool_event();
-    b = pool_event();
-    if (!a || !b) return;
-    on = hipEventRecord(a, s) == hipSuccess;
-  }
-  ~ProfScope() {
-    if (!on) return;
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (hipEventRecord(b, s) == hipSuccess) g_prof_recs.push_back(ProfRec{kind, a, b});
-  }
-};
 
 int march_segment(int n, int nx, int n_other) {
   static int env = -1;

@@ -116,3 +116,38 @@ def test_strerror_and_fields(lib):
     assert lib.tenom_num_fields(C.byref(grid())) == 5
     assert lib.tenom_num_fields(C.byref(grid(ndim=2))) == 4
     assert lib.tenom_num_fields(C.byref(grid(system=0))) == 1
+
+
+def test_batch_arguments_fail_before_allocation(lib):
+    """tenom_batch_create checks its arguments before touching the device."""
+    plan = C.c_void_p()
+    n = (C.c_int64 * 3)(64, 5, 64)
+    dx = (C.c_double * 3)(0.1, 0.1, 0.1)
+    assert lib.tenom_batch_create(3, n, dx, 1, C.byref(plan)) == T.EINVAL  # 5 < 6 cells
+    assert "fewer than 6" in lib.tenom_last_error().decode()
+    n[1] = 64
+    dx[2] = 0.0
+    assert lib.tenom_batch_create(3, n, dx, 1, C.byref(plan)) == T.EINVAL
+    dx[2] = float("inf")
+    assert lib.tenom_batch_create(3, n, dx, 1, C.byref(plan)) == T.EINVAL
+    dx[2] = 0.1
+    assert lib.tenom_batch_create(3, n, dx, 2, C.byref(plan)) == T.EINVAL  # boundary rule
+    assert lib.tenom_batch_create(-1, n, dx, 1, C.byref(plan)) == T.EINVAL
+    assert lib.tenom_batch_create(3, None, dx, 1, C.byref(plan)) == T.EINVAL
+    assert lib.tenom_batch_create(3, n, dx, 1, None) == T.EINVAL
+    assert plan.value is None
+    # calls on a NULL plan
+    assert lib.tenom_batch_rk3(None, 8, 1, 1e-7, 1.4, 0.4, 1, 0, 1, DUMMY, None) == T.EINVAL
+    assert lib.tenom_batch_rk3_graph(None, 8, 1, 1e-7, 1.4, 0.4, 1, DUMMY, None) == T.EINVAL
+    assert lib.tenom_batch_cells(None) == -1
+    assert lib.tenom_batch_get_tile(None) == -1
+    assert lib.tenom_batch_destroy(None) == T.OK
+
+
+def test_batch_tile_shapes(lib):
+    shapes = [T.batch_tile_shape(t) for t in range(T.BATCH_TILES)]
+    assert len(set(shapes)) == T.BATCH_TILES
+    for threads, fpt in shapes:
+        assert threads % 64 == 0 and fpt >= 1  # whole wavefronts
+    with pytest.raises(T.TenomError):
+        T.batch_tile_shape(T.BATCH_TILES)

@@ -1,0 +1,281 @@
+"""GPU parity of the batched path (many independent 1D Euler problems of
+uneven size, tenom_batch_*) against the oracle run problem by problem, and
+its invariants: every tile shape, the graph replay and per-problem launches
+give the same bits; the autotuner leaves the state alone; an empty batch is
+a no-op."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import exact_riemann as ER
+from parity import (RTOL, assert_close_fields, band_faces, conditioning_tol, faces_to_cells, field_scale,
+                    require_gpu, to_dev, to_host, ulp_perturbed)
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+CFL = 0.4
+# ragged sizes around the tile boundaries (63/64/65, 127/128/129, 255/256/257,
+# 511/512/513) and the smallest admissible problems
+SIZES = [8, 9, 13, 63, 64, 65, 127, 128, 129, 254, 255, 256, 257, 300, 511, 512, 513, 700, 1023, 1025]
+
+
+def ragged_batch(sizes, seed0=0):
+    """One seeded Riemann problem per entry (states as W.riemann_states),
+    packed end to end; dx = 1/n on [0, 1]."""
+    parts, dx, states = [], [], []
+    for p, n in enumerate(sizes):
+        left, right = W.riemann_states(seed0 + p)
+        U, h = W.riemann_problem(int(n), left, right, gamma=GAMMA)
+        parts.append(U)
+        dx.append(h)
+        states.append((left, right))
+    return np.concatenate(parts, axis=1), np.array(dx), states
+
+
+def problem(U, plan, p):
+    a, b = plan.offsets[p], plan.offsets[p + 1]
+    return np.ascontiguousarray(U[:, a:b])
+
+
+def grid_of(n, dx, bc):
+    return dict(ndim=1, n=[int(n)], dx=[float(dx)], bc=[bc], system=1)
+
+
+def rk3_excluded(orc, U, grid, scheme, lim, C_T, dt):
+    """Cells whose step depends on a face in the cutoff band at any stage."""
+    L0 = orc.flux_divergence(U, grid, scheme, lim, C_T, GAMMA)
+    U1 = U + dt * L0
+    L1 = orc.flux_divergence(U1, grid, scheme, lim, C_T, GAMMA)
+    U2 = 0.75 * U + 0.25 * (U1 + dt * L1)
+    n = grid["n"][0]
+    excl = np.zeros(n, dtype=bool)
+    for S in (U, U1, U2):
+        _, _, bd = orc.reconstruct_faces(S, grid, scheme, lim, C_T, GAMMA, 0)
+        excl |= faces_to_cells(band_faces(bd), 0, n, grid["bc"][0] == 0, 3 * (scheme & 0xFF) // 2)
+    return excl
+
+
+@pytest.fixture(scope="module")
+def T():
+    require_gpu()
+    import paper_2010_13289_amd as T
+    return T
+
+
+# name, scheme, limiter, C_T, bc
+CASES = [
+    ("tvd8_trans", 8, 2, 1e-7, 1),
+    ("mp8_trans", 8, 1, 1e-7, 1),
+    ("mp6_periodic", 6, 1, 1e-5, 0),
+    ("teno8a_va_trans", 8 | 0x100, 4, 0.0, 1),
+    ("teno6_classic_periodic", 6, 0, 1e-5, 0),
+    ("tvd5_8_periodic", 8, 3, 1e-7, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_batch_steps_match_the_oracle(T, orc, case):
+    """Three steps; each compared problem by problem with the oracle's step
+    from the same input with the step size the device chose, which must be
+    the oracle's CFL step."""
+    name, scheme, lim, C_T, bc = case
+    U, dx, _ = ragged_batch(SIZES, seed0=11)
+    plan = T.BatchPlan(SIZES, dx, bc)
+    Ud = to_dev(U)
+    for step in range(3):
+        print(f"[batch] {name} step {step}", flush=True)
+        Uin = to_host(Ud)
+        plan.rk3(Ud, scheme, lim, C_T, GAMMA, CFL, steps=1)
+        t, dt = plan.times()
+        Ug = to_host(Ud)
+        for p, n in enumerate(SIZES):
+            g = grid_of(n, dx[p], bc)
+            Up = problem(Uin, plan, p)
+            assert dt[p] == pytest.approx(CFL / orc.max_wave_speed(Up, g, GAMMA), rel=1e-13)
+            Uo = orc.rk3_step(Up, g, scheme, lim, C_T, GAMMA, dt[p])
+            excl = rk3_excluded(orc, Up, g, scheme, lim, C_T, dt[p])
+            assert excl.sum() < n // 2, f"problem {p}: {excl.sum()} band cells"
+            assert_close_fields(problem(Ug, plan, p), Uo, exclude=excl, what=f"{name} step {step} problem {p}")
+    t, _ = plan.times()
+    assert np.all(t > 0)
+    plan.close()
+
+
+def test_every_tile_gives_the_same_bits(T):
+    U, dx, _ = ragged_batch(SIZES, seed0=3)
+    plan = T.BatchPlan(SIZES, dx, 1)
+    ref = None
+    for tile in range(T.BATCH_TILES):
+        print(f"[batch] tile {tile} {T.batch_tile_shape(tile)}", flush=True)
+        plan.tile = tile
+        Ud = to_dev(U)
+        plan.rk3(Ud, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=2)
+        out = to_host(Ud)
+        if ref is None:
+            ref = out
+        assert np.array_equal(out, ref), f"tile {tile} differs"
+    plan.close()
+
+
+def test_graph_replays_match_eager_steps(T):
+    """The captured graph equals the eager enqueue in every bit, on the
+    first launch and on replays with other device work in between."""
+    import torch
+    U, dx, _ = ragged_batch(SIZES, seed0=5)
+    plan = T.BatchPlan(SIZES, dx, 1)
+    A = to_dev(U)
+    B = to_dev(U)
+    other = to_dev(U)
+    for replay in range(3):
+        print(f"[batch] graph replay {replay}", flush=True)
+        plan.rk3(A, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=4)
+        plan.rk3_graph(B, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=4)
+        assert np.array_equal(to_host(A), to_host(B)), f"replay {replay}"
+        # unrelated eager work and a synchronisation between replays
+        plan.rk3(other, 6, T.LIM_TVD5, 1e-5, GAMMA, CFL, steps=1)
+        other.mul_(1.0)
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_problem_ranges_match_the_whole_batch(T):
+    """One launch per problem (first = p, count = 1) gives the same bits and
+    clocks as one launch over the batch."""
+    sizes = SIZES[:12]
+    U, dx, _ = ragged_batch(sizes, seed0=21)
+    whole = T.BatchPlan(sizes, dx, 1)
+    single = T.BatchPlan(sizes, dx, 1)
+    A = to_dev(U)
+    B = to_dev(U)
+    whole.rk3(A, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=3)
+    for p in range(len(sizes)):
+        single.rk3(B, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=3, first=p, count=1)
+    assert np.array_equal(to_host(A), to_host(B))
+    assert np.array_equal(whole.times()[0], single.times()[0])
+    # a range touches only its own problems
+    C_ = to_dev(U)
+    whole.rk3(C_, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=1, first=3, count=2)
+    out = to_host(C_)
+    a, b = whole.offsets[3], whole.offsets[5]
+    assert np.array_equal(out[:, :a], U[:, :a]) and np.array_equal(out[:, b:], U[:, b:])
+    assert not np.array_equal(out[:, a:b], U[:, a:b])
+    whole.close()
+    single.close()
+
+
+def test_autotune_keeps_state_and_clocks(T):
+    U, dx, _ = ragged_batch(SIZES, seed0=8)
+    plan = T.BatchPlan(SIZES, dx, 1)
+    Ud = to_dev(U)
+    plan.rk3(Ud, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=1)
+    before = to_host(Ud)
+    t0, dt0 = plan.times()
+    best, ms = plan.autotune(Ud, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=2)
+    assert 0 <= best < T.BATCH_TILES and plan.tile == best
+    assert all(m > 0 for m in ms) and ms[best] == min(ms)
+    assert np.array_equal(to_host(Ud), before)
+    t1, dt1 = plan.times()
+    assert np.array_equal(t0, t1) and np.array_equal(dt0, dt1)
+    plan.close()
+
+
+def test_empty_batch_and_errors(T):
+    import torch
+    plan = T.BatchPlan([], [], 1)
+    assert plan.total == 0
+    U = torch.empty((3, 0), dtype=torch.float64, device="cuda")
+    plan.rk3(U, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=5)
+    plan.rk3_graph(U, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=5)
+    assert plan.autotune(U, 8, T.LIM_MP, 1e-7, GAMMA, CFL)[0] == plan.tile
+    assert plan.times()[0].size == 0
+    plan.close()
+    # a 6-cell problem admits K = 6 but not K = 8
+    Ub, dx, _ = ragged_batch([6, 40])
+    plan = T.BatchPlan([6, 40], dx, 1)
+    Ud = to_dev(Ub)
+    plan.rk3(Ud, 6, T.LIM_MP, 1e-5, GAMMA, CFL)
+    for args, code in (((8, T.LIM_MP, 1e-7, GAMMA, CFL), T.EINVAL), ((6, T.LIM_MP, 1e-5, GAMMA, 0.0), T.EINVAL),
+                       ((6, 99, 1e-5, GAMMA, CFL), T.EUNSUPPORTED), ((6, T.LIM_MP, 1e-5, 1.0, CFL), T.EINVAL)):
+        with pytest.raises(T.TenomError) as e:
+            plan.rk3(Ud, *args)
+        assert e.value.code == code
+    with pytest.raises(T.TenomError) as e:
+        plan.rk3(Ud, 6, T.LIM_MP, 1e-5, GAMMA, CFL, first=1, count=2)
+    assert e.value.code == T.EINVAL
+    with pytest.raises(T.TenomError):
+        plan.rk3(Ud, 6, T.LIM_MP, 1e-5, GAMMA, CFL, steps=-1)
+    torch.cuda.synchronize()
+    plan.close()
+
+
+def test_batched_4096_problems_graph_100_steps(T, orc):
+    """The benchmark's batch: 4096 problems, n log-uniform in [256, 16384],
+    TENO8-M-MP, 100 steps in one graph launch.  Checks: every problem equals
+    the oracle run problem by problem on 12 sampled problems (tolerance
+    from the oracle's own one-ulp sensitivity over the run), conservation
+    of every problem to round-off (no wave reaches an end in 100 steps),
+    positivity, and the exact solution as a loose physics check."""
+    import torch
+    sizes = W.batched_riemann_sizes()
+    U, dx, states = ragged_batch(sizes)
+    plan = T.BatchPlan(sizes, dx, 1)
+    Ud = to_dev(U)
+    best, ms = plan.autotune(Ud, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=1)
+    print(f"[batch 4096] autotuned tile {best} {T.batch_tile_shape(best)}, ms/step {ms}", flush=True)
+    plan.rk3_graph(Ud, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=100)
+    torch.cuda.synchronize()
+    t, _ = plan.times()
+    Ug = to_host(Ud)
+    assert np.all(np.isfinite(Ug)) and np.all(Ug[0] > 0)
+    rho, m, E = Ug
+    assert np.all(E - 0.5 * m * m / rho > 0)
+    # conservation per problem: no wave reaches an end in 100 steps (only
+    # round-off-level precursors do), so sum(U) changes by the flux through
+    # the two ends, t (F(U_first) - F(U_last)) / dx
+    seg_sum = lambda A: np.add.reduceat(A, plan.offsets[:-1], axis=1)
+    before, after = seg_sum(U), seg_sum(Ug)
+    first, last = U[:, plan.offsets[:-1]], U[:, plan.offsets[1:] - 1]
+
+    def flux(S):
+        rho_, m_, E_ = S
+        u_ = m_ / rho_
+        p_ = (GAMMA - 1.0) * (E_ - 0.5 * m_ * u_)
+        return np.array([m_, m_ * u_ + p_, u_ * (E_ + p_)])
+
+    expect = t / dx * (flux(first) - flux(last))
+    scale = seg_sum(np.abs(U)) + np.abs(expect)
+    assert np.all(np.abs(after - before - expect) <= 1e-12 * scale)
+    # sampled problems against the oracle (its own dt each step)
+    rng = np.random.default_rng(4096)
+    order = np.argsort(sizes)
+    pick = np.concatenate([order[:6], rng.choice(order[6:2000], size=6, replace=False)])
+    for p in pick:
+        n = int(sizes[p])
+        g = grid_of(n, dx[p], 1)
+        print(f"[batch 4096] oracle run of problem {p} (n = {n})", flush=True)
+
+        def run(S):
+            tt = 0.0
+            for _ in range(100):
+                h = CFL / orc.max_wave_speed(S, g, GAMMA)
+                S = orc.rk3_step(S, g, 8, 1, 1e-7, GAMMA, h)
+                tt += h
+            return S, tt
+
+        U0 = problem(U, plan, p)
+        Uo, to = run(U0)
+        Up, _ = run(ulp_perturbed(U0, seed=int(p)))
+        tol, _ = conditioning_tol(Uo.T, Up.T, field_scale(Uo), factor=8.0)
+        err = np.abs(problem(Ug, plan, p) - Uo)
+        assert np.all(err <= tol[:, None]), (p, (err / tol[:, None]).max())
+        assert t[p] == pytest.approx(to, rel=1e-12)
+        left, right = states[p]
+        x = W.cell_centres(n, 0.0, 1.0)
+        rho_ex, _, _ = ER.sample(left, right, (x - 0.5) / t[p], GAMMA)
+        # L1 error in cells, over the exact density's total variation: at
+        # most 0.82 on 200 seeded problems of the oracle at n = 256
+        l1_cells = np.sum(np.abs(problem(Ug, plan, p)[0] - rho_ex))
+        tv = np.sum(np.abs(np.diff(rho_ex)))
+        assert l1_cells <= 1.5 * tv, (p, l1_cells, tv)
+    plan.close()
