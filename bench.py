@@ -18,6 +18,12 @@ Prints one JSON line.  Inputs are resident in HBM before timing starts.
         one JSON line with the cost of the same RK3 step for every scheme
         (TENO6, TENO8, TENO8A) and limiter, relative to classic TENO of the
         same scheme, in the manner of the paper's Table 2
+    python bench.py --adjoint [--adj-steps 200] [--fd-directions 16]
+        one JSON line for the adjoint: 2D Euler 1024^2 periodic (density
+        modes + circular jump, at rest), TENO6-M-MP, 200 fixed steps, loss =
+        L2 density misfit against a target run; forward, checkpointed
+        forward + backward (checkpoint every 20 steps), and central
+        differences of the loss along random directions
     python bench.py --batched [--batch-steps 100] [--per-problem-steps 3]
         one JSON line for the batched path: 4096 independent 1D Euler
         Riemann problems, n log-uniform in [256, 16384] (15.9 M cells),
@@ -100,6 +106,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--variants", action="store_true")
     ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--adjoint", action="store_true")
+    ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--adj-n", type=int, default=1024)
+    ap.add_argument("--fd-directions", type=int, default=16)
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--per-problem-steps", type=int, default=3)
     return ap.parse_args()
@@ -116,6 +126,117 @@ def parse():
 #   back-projection with R                                  20
 #   divergence and stage update, once per cell              18
 FLOPS_PER_FACE_VECTOR_1D_K8 = 2193
+
+
+def run_adjoint(args):
+    """The adjoint workload; returns the JSON object.
+
+    Timing: TENO6-M-MP (C_T = 1e-5) on the configured state.  The fluid is
+    at rest at uniform pressure, so its acoustic characteristic fields carry
+    only rounding-level signals whose cutoff decisions are set by rounding:
+    the loss is not differentiable at any scale differences can resolve.
+    The difference check therefore runs the same grid, state, steps and
+    checkpointing with C_T = 0 (every candidate smooth, no decision), where
+    the rollout is smooth; the MP gradient's size is reported beside it."""
+    import numpy as np
+    import torch
+
+    import paper_2010_13289_amd as T
+    import workloads as W
+    n, steps, ck = args.adj_n, args.adj_steps, 20
+    U0h, dx = W.density_modes_2d(n, seed=5)
+    T0h, _ = W.density_modes_2d(n, seed=6)
+    grid = dict(ndim=2, n=[n, n], dx=[dx, dx], bc=[0, 0], system=1)
+    scheme, lim = 6, T.LIM_MP
+    U0 = torch.from_numpy(U0h).to("cuda")
+    dt = CFL / T.max_wave_speed(U0, grid, GAMMA)
+    ws = T.Workspace(grid, scheme, U0.device)
+
+    def forward(U, ct):
+        V = U.clone()
+        for _ in range(steps):
+            T.rk3_step(V, grid, scheme, lim, ct, GAMMA, dt, workspace=ws)
+        return V
+
+    def loss_fn(ct):
+        rho_T = forward(torch.from_numpy(T0h).to("cuda"), ct)[0].clone()
+        return lambda Uf: 0.5 * ((Uf[0] - rho_T) ** 2).sum() * dx * dx
+
+    def grad(ct, loss_of):
+        U = U0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = loss_of(T.rollout(U, grid, scheme, lim, ct, GAMMA, dt, steps, checkpoint=ck))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        T.profile_read()
+        T.profile_enable(True)
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        T.profile_enable(False)
+        return U.grad.detach(), float(L.item()), t1 - t0, t2 - t1, T.profile_read()
+
+    # timing on the configured scheme
+    ct = 1e-5
+    loss_mp = loss_fn(ct)
+    forward(U0, ct)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    forward(U0, ct)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    g_mp, L_mp, t_fwd_ck, t_bwd, prof = grad(ct, loss_mp)
+    # difference check with C_T = 0
+    loss0 = loss_fn(0.0)
+    g0, L0, _, _, _ = grad(0.0, loss0)
+    rng = np.random.default_rng(2010)
+    scale = np.maximum(np.abs(U0h).max(axis=(1, 2)), 1.0)[:, None, None]
+    rows = []
+    with torch.no_grad():
+        for d in range(args.fd_directions):
+            V = torch.from_numpy(rng.standard_normal(U0h.shape) * scale).to("cuda")
+            fd = []
+            for h in (1e-5, 1e-6):
+                lp = loss0(forward(U0 + h * V, 0.0)).item()
+                lm = loss0(forward(U0 - h * V, 0.0)).item()
+                fd.append((lp - lm) / (2 * h))
+            ad = float((g0 * V).sum().item())
+            rows.append({"fd_h1e-5": fd[0], "fd_h1e-6": fd[1], "adjoint": ad,
+                         "rel_err": abs(fd[1] - ad) / max(abs(ad), 1e-300)})
+    vjp_n, vjp_ms = prof["vjp_axis"]
+    faces = 2 * n * n
+    return {
+        "metric": METRIC,
+        "value": 3 * steps * faces / t_bwd,
+        "unit": "face adjoints/s (backward pass, recomputation included)",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 1,
+        "ms_per_step": t_bwd / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2D Euler {n}^2 periodic: density 1 + 64 seeded Fourier modes (|k| <= 32, amplitude "
+                        "0.05), x0.5 inside a circle of radius 0.2, u = v = 0, p = 1; TENO6-M-MP, C_T=1e-5, "
+                        f"gamma=1.4, {steps} SSP-RK3 steps of fixed dt (CFL 0.4 at t=0); loss = L2 density "
+                        "misfit against the run from seed 6; adjoint checkpointed every 20 steps",
+            "grid": [n, n],
+        },
+        "forward_s": t_fwd,
+        "forward_with_checkpoints_s": t_fwd_ck,
+        "backward_s": t_bwd,
+        "backward_over_forward": t_bwd / t_fwd,
+        "vjp_axis_avg_ms": vjp_ms / max(vjp_n, 1),
+        "vjp_axis_launches": vjp_n,
+        "loss": L_mp,
+        "mp_gradient_max_per_field": g_mp.abs().amax(dim=(1, 2)).cpu().tolist(),
+        "fd_check_ct0": {"directions": len(rows), "loss": L0,
+                         "max_rel_err": max(r["rel_err"] for r in rows) if rows else None, "rows": rows},
+    }
 
 
 def run_batched(args):
@@ -338,6 +459,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.batched:
         print(json.dumps(run_batched(args)), flush=True)
+        return
+    if args.adjoint:
+        print(json.dumps(run_adjoint(args)), flush=True)
         return
     n = args.n
     U_host, dx = W.tgv_3d(n, gamma=GAMMA)

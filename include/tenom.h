@@ -173,6 +173,55 @@ int tenom_max_wave_speed(const tenom_grid* grid, double gamma, const double* U, 
  * Synchronises `stream`. */
 int tenom_check_finite(const tenom_grid* grid, const double* U, void* stream);
 
+/* ---- adjoint ------------------------------------------------------------- */
+/*
+ * Vector-Jacobian products of the flux divergence and of one SSP-RK3 step,
+ * for gradients through rollouts (loss functions of the final state).
+ * Each is the exact derivative of the forward map with every
+ * piecewise choice frozen at the state it is evaluated on:
+ *   - the smoothness decisions delta_k (the cutoff, Eq. cut-off; adaptive
+ *     C_T of Sec. 2.4);
+ *   - the limiter branches (min/max, minmod and median selections of
+ *     Secs. 3.2.1-3.2.2);
+ *   - the cell attaining the Rusanov alpha.
+ * With these frozen, the reconstruction with optimal weights (Eq.
+ * reconstuction) is linear in the split fluxes.  Van Albada's slope function
+ * (Eq. van_Albada_limiter) is differentiated as it stands.  Ties go to the
+ * first argument of a min/max; a minmod passes the derivative to its
+ * smallest-magnitude argument only when all arguments share a strict sign;
+ * alpha's derivative goes to its first maximising cell, and |u_n| in the
+ * signal speed passes sgn(u_n) (0 at u_n = 0).  dt is a parameter (not
+ * differentiated).
+ */
+
+/* Workspace bytes tenom_flux_divergence_vjp needs (0 if invalid): one
+ * contribution per face, stencil slot and field of the largest axis. */
+size_t tenom_vjp_workspace_bytes(const tenom_grid* grid, int scheme);
+
+/*
+ * Ubar = (accumulate ? Ubar : 0) + scale * (d L / d U)^T Lbar, where
+ * L(U) = tenom_flux_divergence(U).  U, Lbar, Ubar: device arrays of the
+ * state's shape; Ubar must not alias U or Lbar.  ws: device workspace of
+ * tenom_vjp_workspace_bytes.  Deterministic (no atomics).
+ */
+int tenom_flux_divergence_vjp(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma,
+                              const double* U, const double* Lbar, double scale, double* Ubar, int accumulate,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes tenom_rk3_step_vjp needs: five states plus the above. */
+size_t tenom_rk3_vjp_workspace_bytes(const tenom_grid* grid, int scheme);
+
+/*
+ * Adjoint of one tenom_rk3_step from the state U (the step's input, not
+ * modified) with step dt: on entry Ubar holds the cotangent of the step's
+ * output, on return that of its input.  The stage states are recomputed by
+ * the forward sweeps into the workspace (256-byte aligned, at least
+ * tenom_rk3_vjp_workspace_bytes), so every decision is the one the forward
+ * step took.
+ */
+int tenom_rk3_step_vjp(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                       const double* U, double* Ubar, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- batched independent 1D problems ------------------------------------ */
 /*
  * Many independent 1D Euler problems of uneven size (the shock tubes of
@@ -273,10 +322,11 @@ int tenom_version(void);
  * launches and their summed duration in milliseconds since the last reset.
  * Kinds: 0 face fluxes (reconstruct_faces), 1 x-sweep, 2 y-sweep,
  * 3 z-sweep, 4 batched sweep, 5 batched step size, 6 one replay of a batched
- * graph (kernels inside a graph are not bracketed one by one).  At most 4096
- * launches are recorded between reads.
+ * graph (kernels inside a graph are not bracketed one by one), 7 one axis of
+ * an adjoint (face kernel + gather).  At most 4096 launches are recorded
+ * between reads.
  */
-#define TENOM_KERNEL_KINDS 7
+#define TENOM_KERNEL_KINDS 8
 int tenom_profile_enable(int on);
 int tenom_profile_read(int64_t* counts, double* total_ms, int nkinds);
 

@@ -27,7 +27,8 @@ forward map with all of them frozen at the evaluation point:
     first argument on ties and a minmod passing it to its
     smallest-magnitude argument only when all its arguments share a
     strict sign;
-  - the Rusanov alpha, at its first maximising cell.
+  - the Rusanov alpha, at its first maximising cell, with |u_n| passing
+    sgn(u_n) (0 at u_n = 0, torch.abs's convention).
 That is the derivative the GPU adjoint computes.  The time step is a
 parameter.  Pinned in ``tests/test_oracle_adjoint.py`` against the C oracle's
 values and against central differences of the C oracle.

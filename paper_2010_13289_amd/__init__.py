@@ -25,7 +25,7 @@ SCHEME_ADAPTIVE = 0x100
 SCHEME_8A = SCHEME_8 | SCHEME_ADAPTIVE   # eight points, adaptive cutoff (TENO8A)
 LIM_TENO, LIM_MP, LIM_TVD_MINMOD, LIM_TVD5, LIM_VA = 0, 1, 2, 3, 4
 LIM_MP_M4_B2, LIM_MP_MM_B4, LIM_MP_MM_B2, LIM_MP_MM_B1 = 5, 6, 7, 8
-KERNEL_KINDS = ("faces", "sweep_x", "sweep_y", "sweep_z", "batch_sweep", "batch_dt", "batch_graph")
+KERNEL_KINDS = ("faces", "sweep_x", "sweep_y", "sweep_z", "batch_sweep", "batch_dt", "batch_graph", "vjp_axis")
 BATCH_TILES = 6
 
 SYMBOLS = (
@@ -35,6 +35,8 @@ SYMBOLS = (
     "tenom_batch_tile_shape", "tenom_batch_create", "tenom_batch_destroy", "tenom_batch_cells",
     "tenom_batch_set_tile", "tenom_batch_get_tile", "tenom_batch_rk3", "tenom_batch_rk3_graph",
     "tenom_batch_autotune", "tenom_batch_times", "tenom_batch_reset_times",
+    "tenom_vjp_workspace_bytes", "tenom_flux_divergence_vjp", "tenom_rk3_vjp_workspace_bytes",
+    "tenom_rk3_step_vjp",
 )
 
 
@@ -136,6 +138,13 @@ def lib() -> C.CDLL:
                                            C.POINTER(ip), vp]
         L.tenom_batch_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
         L.tenom_batch_reset_times.argtypes = [vp, vp]
+        L.tenom_vjp_workspace_bytes.argtypes = [gp, C.c_int]
+        L.tenom_vjp_workspace_bytes.restype = C.c_size_t
+        L.tenom_rk3_vjp_workspace_bytes.argtypes = [gp, C.c_int]
+        L.tenom_rk3_vjp_workspace_bytes.restype = C.c_size_t
+        L.tenom_flux_divergence_vjp.argtypes = [gp, C.c_int, C.c_int, dp, dp, vp, vp, dp, vp, C.c_int, vp,
+                                                C.c_size_t, vp]
+        L.tenom_rk3_step_vjp.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, vp, C.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -359,3 +368,121 @@ class BatchPlan:
 
     def reset_times(self, stream=None):
         _check(lib().tenom_batch_reset_times(self._h, _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+class _Buffer:
+    """Device workspace owned by a torch uint8 tensor (256-byte aligned)."""
+
+    def __init__(self, nbytes: int, device):
+        import torch
+        if nbytes == 0:
+            raise TenomError(EINVAL, "invalid grid or scheme for a workspace")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+
+def vjp_workspace(grid, scheme: int, device="cuda") -> _Buffer:
+    g = Grid.of(grid).to_c()
+    return _Buffer(int(lib().tenom_vjp_workspace_bytes(C.byref(g), scheme)), device)
+
+
+def rk3_vjp_workspace(grid, scheme: int, device="cuda") -> _Buffer:
+    g = Grid.of(grid).to_c()
+    return _Buffer(int(lib().tenom_rk3_vjp_workspace_bytes(C.byref(g), scheme)), device)
+
+
+def flux_divergence_vjp(U, Lbar, grid, scheme: int, limiter: int, C_T: float, gamma: float, out=None,
+                        scale: float = 1.0, accumulate: bool = False, workspace=None, stream=None):
+    """out (+)= scale * (dL/dU)^T Lbar for L = flux_divergence; returns out."""
+    import torch
+    g = Grid.of(grid)
+    up, lp = _state(U, g), _state(Lbar, g, "Lbar")
+    if out is None:
+        out = torch.empty_like(U)
+        accumulate = False
+    op = _state(out, g, "out")
+    ws = workspace if workspace is not None else vjp_workspace(g, scheme, U.device)
+    gc = g.to_c()
+    _check(lib().tenom_flux_divergence_vjp(C.byref(gc), scheme, limiter, C_T, gamma, up, lp, float(scale), op,
+                                           1 if accumulate else 0, ws.ptr, ws.nbytes, _stream(stream)))
+    return out
+
+
+def rk3_step_vjp(U, Ubar, grid, scheme: int, limiter: int, C_T: float, gamma: float, dt: float, workspace=None,
+                 stream=None):
+    """Ubar <- (d step(U) / d U)^T Ubar, in place; U is the step's input."""
+    g = Grid.of(grid)
+    up, bp = _state(U, g), _state(Ubar, g, "Ubar")
+    ws = workspace if workspace is not None else rk3_vjp_workspace(g, scheme, U.device)
+    gc = g.to_c()
+    _check(lib().tenom_rk3_step_vjp(C.byref(gc), scheme, limiter, C_T, gamma, dt, up, bp, ws.ptr, ws.nbytes,
+                                    _stream(stream)))
+    return Ubar
+
+
+def _rollout_forward(U0, g, scheme, limiter, C_T, gamma, dt, steps, checkpoint, ws):
+    U = U0.detach().clone()
+    saved = []
+    for s in range(steps):
+        if s % checkpoint == 0:
+            saved.append(U.clone())
+        rk3_step(U, g, scheme, limiter, C_T, gamma, dt, workspace=ws)
+    return U, saved
+
+
+class Rk3Rollout:
+    """`steps` SSP-RK3 steps of fixed size dt as a differentiable torch op.
+
+    The forward keeps the state every `checkpoint` steps; the backward
+    replays each segment from its checkpoint (the same kernels, so the same
+    decisions) and applies tenom_rk3_step_vjp in reverse order.  Memory:
+    steps/checkpoint + checkpoint states."""
+
+    @staticmethod
+    def apply(U0, grid, scheme, limiter, C_T, gamma, dt, steps, checkpoint=20):
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, U0_):
+                g = Grid.of(grid)
+                ws = Workspace(g, scheme, U0_.device)
+                U, saved = _rollout_forward(U0_, g, scheme, limiter, C_T, gamma, dt, steps, checkpoint, ws)
+                ctx.saved = saved
+                return U
+
+            @staticmethod
+            def backward(ctx, Ubar):
+                g = Grid.of(grid)
+                ws = Workspace(g, scheme, Ubar.device)
+                vws = rk3_vjp_workspace(g, scheme, Ubar.device)
+                lam = Ubar.detach().clone().contiguous()
+                nseg = len(ctx.saved)
+                for k in range(nseg - 1, -1, -1):
+                    first = k * checkpoint
+                    last = min(steps, first + checkpoint)
+                    states = [ctx.saved[k].clone()]
+                    for _ in range(first, last - 1):
+                        V = states[-1].clone()
+                        rk3_step(V, g, scheme, limiter, C_T, gamma, dt, workspace=ws)
+                        states.append(V)
+                    for V in reversed(states):
+                        rk3_step_vjp(V, lam, g, scheme, limiter, C_T, gamma, dt, workspace=vws)
+                ctx.saved = None
+                return lam
+
+        return _Fn.apply(U0)
+
+
+def rollout(U0, grid, scheme: int, limiter: int, C_T: float, gamma: float, dt: float, steps: int,
+            checkpoint: int = 20):
+    """Differentiable `steps`-step rollout (see Rk3Rollout)."""
+    return Rk3Rollout.apply(U0, grid, scheme, limiter, C_T, gamma, dt, steps, checkpoint)

@@ -1,9 +1,9 @@
 """Build libtenom.so (HIP, gfx950) in-tree.
 
 Steps: regenerate csrc/teno_tables.h from gen_tables.py, compile the eight
-instantiation units (fields x K), the six batched-path units (one per tile
-shape) and the two C-ABI sources in parallel with hipcc, link them into
-paper_2010_13289_amd/libtenom.so.
+forward and the eight adjoint instantiation units (fields x K), the six
+batched-path units (one per tile shape) and the two C-ABI sources in
+parallel with hipcc, link them into paper_2010_13289_amd/libtenom.so.
 
     python -m paper_2010_13289_amd.build [--verbose]
 """
@@ -77,10 +77,11 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     cmds = []
     objs = []
     for nf, k in UNITS:
-        obj = os.path.join(BUILD, f"inst_nf{nf}_k{k}.o")
-        objs.append(obj)
-        cmds.append([hipcc, *HIPCC_FLAGS, f"-DTENOM_NF={nf}", f"-DTENOM_K={k}", "-c",
-                     os.path.join(CSRC, "tenom_inst.hip"), "-o", obj])
+        for unit in ("inst", "vjp"):
+            obj = os.path.join(BUILD, f"{unit}_nf{nf}_k{k}.o")
+            objs.append(obj)
+            cmds.append([hipcc, *HIPCC_FLAGS, f"-DTENOM_NF={nf}", f"-DTENOM_K={k}", "-c",
+                         os.path.join(CSRC, "tenom_inst.hip" if unit == "inst" else "tenom_vjp_inst.hip"), "-o", obj])
     for t in range(BATCH_TILES):
         obj = os.path.join(BUILD, f"batch_tile{t}.o")
         objs.append(obj)

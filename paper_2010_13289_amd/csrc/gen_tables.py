@@ -180,6 +180,7 @@ def emit(K: int) -> str:
     w("  // candidate fluxes minus v_i, from the candidate stencils of Table 1")
     w("  static __device__ __forceinline__ void candidates(const double* D, double* c) {")
     names = [f"D[{j}]" for j in range(K - 1)]
+    cand_coefs = []
     for k in range(nk):
         a, b = CANDIDATES[k]
         fc = face_coeffs(a, b)
@@ -194,6 +195,15 @@ def emit(K: int) -> str:
                 for j in range(idx, c0):
                     coefs[j] -= fc[jj]
         w(f"    c[{k}] = {linear_form(coefs, names)};")
+        cand_coefs.append(coefs)
+    w("  }")
+    # transpose of the candidate map, for the adjoint: Dbar += C^T cbar
+    w("  // adjoint of candidates: Dbar[j] += sum_k (d c_k / d D_j) cbar[k]")
+    w("  static __device__ __forceinline__ void candidates_vjp(const double* cbar, double* Dbar) {")
+    for j in range(K - 1):
+        col = [cand_coefs[k][j] for k in range(nk)]
+        if any(c != 0 for c in col):
+            w(f"    Dbar[{j}] = {linear_form(col + [Fr(1)], [f'cbar[{k}]' for k in range(nk)] + [f'Dbar[{j}]'])};")
     w("  }")
     # betas
     w("  // smoothness measures beta_k (candidates) and beta_K (full stencil)")

@@ -68,27 +68,27 @@ __device__ __forceinline__ double rcp1(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// One TENO-M reconstruction at x_{i+1/2} from v[0..K-1] = f_{i-K/2+1..i+K/2}
-// (Secs. 2.2-3.3).  Computed relative to v_i, in differences of adjacent
-// values.  `bits` receives delta_k (1 = smooth) in bit k when FLAGS.
-// The inputs are twice the split fluxes (lf_split2) and so is the result:
-// every step is homogeneous, with eps scaled to match, so the result is
-// exactly twice the reconstruction of the halved values.
+// Pieces of one TENO-M reconstruction at x_{i+1/2} from v[0..K-1] =
+// f_{i-K/2+1..i+K/2} (Secs. 2.2-3.3), computed relative to v_i in the
+// differences D[j] = v[j+1] - v[j].  The inputs are twice the split fluxes
+// (lf_split2) and so is the result: every step is homogeneous, with eps
+// scaled to match, so the result is exactly twice the reconstruction of the
+// halved values.  The forward reconstruction (teno_m) and its adjoint share
+// these functions, so both take the same decisions.
 // ---------------------------------------------------------------------------
-template <int K, int LIM, bool FLAGS, bool ADAPT>
-__device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams& tp, uint32_t& bits) {
+
+// Smoothness decisions delta_k (true = smooth): indicators, tau_K, gamma_k
+// and the cutoff (Eqs. measureTENO, taukTENO, normalize, cut-off); with
+// ADAPT the cutoff of Sec. 2.4 (Eqs. shock_indicator, cut-off_adjust).
+template <int K, bool ADAPT>
+__device__ __forceinline__ void teno_cutoff(const double (&D)[K - 1], const TenoParams& tp, bool (&smooth)[K - 2]) {
   using T = TenoTables<K>;
   constexpr int NK = K - 2;
   constexpr int C0 = K / 2 - 1;  // index of v_i
-
-  double D[K - 1];
-#pragma unroll
-  for (int j = 0; j < K - 1; ++j) D[j] = v[j + 1] - v[j];
-
   double C_T = tp.C_T;
   if constexpr (ADAPT) {
-    // Eq. shock_indicator: eta at cells i-1 .. i+2 (eps scaled by 4 for the
-    // doubled values), the minimum, m = 1 - min(1, eta / C_r)
+    // eta at cells i-1 .. i+2 (eps scaled by 4 for the doubled values), the
+    // minimum, m = 1 - min(1, eta / C_r)
     double eta = 0.0;
 #pragma unroll
     for (int j = C0 - 1; j <= C0 + 2; ++j) {
@@ -99,23 +99,16 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
       eta = (j == C0 - 1) ? e : fmin(eta, e);
     }
     const double m = 1.0 - fmin(1.0, eta * (1.0 / kRenCr));
-    // Eq. cut-off_adjust: g = (1-m)^4 (1+4m), beta = 10.5 - 3.5 (1 - g),
-    // C_T = 10^-floor(beta) with floor(beta) in {7, 8, 9, 10}
+    // g = (1-m)^4 (1+4m), beta = 10.5 - 3.5 (1 - g), C_T = 10^-floor(beta)
+    // with floor(beta) in {7, 8, 9, 10}
     const double om = 1.0 - m, om2 = om * om;
     const double g = om2 * om2 * fma(4.0, m, 1.0);
     const double fl = floor(fma(-3.5, 1.0 - g, 10.5));
     C_T = fl >= 10.0 ? 1e-10 : (fl >= 9.0 ? 1e-9 : (fl >= 8.0 ? 1e-8 : 1e-7));
   }
-
-  // candidate fluxes (Table 1), minus v_i
-  double c[NK];
-  T::candidates(D, c);
-
-  // smoothness indicators and the global tau_K (Eqs. measureTENO, taukTENO)
   double beta[NK], betaK;
   T::betas(D, beta, betaK);
   const double tau = fabs(fma(fma(4.0, beta[0], beta[1] + beta[2]), -1.0 / 6.0, betaK));
-
   // gamma_k and the cutoff: chi_k = gamma_k / sum < C_T  <=>  gamma_k < C_T sum
   double g[NK];
   double sum = 0.0;
@@ -128,49 +121,110 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
     sum = fma(s4, s2, sum);  // the sum takes gamma_k unrounded
   }
   const double thr = C_T * sum;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) smooth[k] = !(g[k] < thr);
+}
+
+// MP bounds relative to v_i (Eqs. curvature, maximal_curvature or
+// maximal_curvature1, upper_limiter, median_value, large_curvature,
+// value_min_max), with every intermediate the adjoint needs.
+struct MpState {
+  double d_im1, d_i, d_ip1;  // curvatures at i-1, i, i+1
+  double aR[4], aL[4];       // minmod arguments at i+1/2 and i-1/2
+  double dR, dL;             // curvature measures at i+1/2 and i-1/2
+  double ul, md, lc;
+  double lo, hi;             // f_min - f_i, f_max - f_i
+};
+
+template <int K, int LIM>
+__device__ __forceinline__ void mp_bounds(const double (&D)[K - 1], const TenoParams& tp, MpState& s) {
+  constexpr int C0 = K / 2 - 1;
+  const double dm = D[C0 - 1];  // f_i - f_{i-1}
+  const double dp = D[C0];      // f_{i+1} - f_i
+  s.d_im1 = D[C0 - 1] - D[C0 - 2];
+  s.d_i = D[C0] - D[C0 - 1];
+  s.d_ip1 = D[C0 + 1] - D[C0];
+  if constexpr (LIM == LIM_MP) {
+    s.aR[0] = fma(4.0, s.d_i, -s.d_ip1);
+    s.aR[1] = fma(4.0, s.d_ip1, -s.d_i);
+    s.aR[2] = s.d_i;
+    s.aR[3] = s.d_ip1;
+    s.aL[0] = fma(4.0, s.d_im1, -s.d_i);
+    s.aL[1] = fma(4.0, s.d_i, -s.d_im1);
+    s.aL[2] = s.d_im1;
+    s.aL[3] = s.d_i;
+    s.dR = minmod4(s.aR[0], s.aR[1], s.aR[2], s.aR[3]);
+    s.dL = minmod4(s.aL[0], s.aL[1], s.aL[2], s.aL[3]);
+  } else {
+    s.aR[0] = s.d_i;
+    s.aR[1] = s.d_ip1;
+    s.aL[0] = s.d_im1;
+    s.aL[1] = s.d_i;
+    s.dR = minmod2(s.d_i, s.d_ip1);
+    s.dL = minmod2(s.d_im1, s.d_i);
+  }
+  // alpha = 1.25; 0 (= f_i) lies in both brackets, so lo <= 0 <= hi
+  s.ul = 1.25 * dm;
+  s.md = fma(0.5, dp, -0.5 * s.dR);
+  s.lc = fma(tp.mp_beta3, s.dL, 0.5 * dm);
+  s.lo = fmax(fmin(fmin(0.0, dp), s.md), fmin(fmin(0.0, s.ul), s.lc));
+  s.hi = fmin(fmax(fmax(0.0, dp), s.md), fmax(fmax(0.0, s.ul), s.lc));
+}
+
+// TVD5 flux on the five cells centred at i, relative to v_i (Eqs. high order
+// TVD, TVDhighorder2, TVDbeta multiplied through by delta^-: division-free,
+// equal wherever the slope ratios exist).
+template <int K>
+__device__ __forceinline__ double tvd5_b(const double (&D)[K - 1]) {
+  constexpr int C0 = K / 2 - 1;
+  return fma(-3.0, D[C0 + 1], fma(24.0, D[C0], fma(11.0, D[C0 - 1], -2.0 * D[C0 - 2]))) * (1.0 / 30.0);
+}
+
+// Van Albada with kappa = 1/3 (Eqs. van_Albada_limiter, slop_ratio, vAflux):
+// phi = 2 r/(r^2 + 1) = 2 d+ d- / (d+^2 + d-^2), 0 when both vanish.
+// Branch-free: the denominator is raised to the smallest normal, which
+// changes nothing unless |d+|, |d-| < 1e-154, and gives 0 * finite = 0 when
+// both differences vanish.
+constexpr double kVaDenMin = 2.2250738585072014e-308;
+
+__device__ __forceinline__ double va_den(double dm, double dp) { return fmax(fma(dp, dp, dm * dm), kVaDenMin); }
+
+// One TENO-M reconstruction (Secs. 2.2-3.3).  `bits` receives delta_k
+// (1 = smooth) in bit k when FLAGS.
+template <int K, int LIM, bool FLAGS, bool ADAPT>
+__device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams& tp, uint32_t& bits) {
+  using T = TenoTables<K>;
+  constexpr int NK = K - 2;
+  constexpr int C0 = K / 2 - 1;  // index of v_i
+
+  double D[K - 1];
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) D[j] = v[j + 1] - v[j];
+
+  // candidate fluxes (Table 1), minus v_i
+  double c[NK];
+  T::candidates(D, c);
+  bool smooth[NK];
+  teno_cutoff<K, ADAPT>(D, tp, smooth);
 
   // limiter on the nonsmooth candidates (Eq. mp_flux), relative to v_i
   const double dm = D[C0 - 1];  // f_i - f_{i-1}
   const double dp = D[C0];      // f_{i+1} - f_i
   double lo = 0.0, hi = 0.0, ftvd = 0.0;
   if constexpr (LIM == LIM_MP || LIM == LIM_MP_MM) {
-    // curvatures (Eq. curvature); d^M4 (Eq. maximal_curvature) or d^MM
-    // (Eq. maximal_curvature1) at i -+ 1/2
-    const double d_im1 = D[C0 - 1] - D[C0 - 2];
-    const double d_i = D[C0] - D[C0 - 1];
-    const double d_ip1 = D[C0 + 1] - D[C0];
-    double dR, dL;
-    if constexpr (LIM == LIM_MP) {
-      dR = minmod4(fma(4.0, d_i, -d_ip1), fma(4.0, d_ip1, -d_i), d_i, d_ip1);
-      dL = minmod4(fma(4.0, d_im1, -d_i), fma(4.0, d_i, -d_im1), d_im1, d_i);
-    } else {
-      dR = minmod2(d_i, d_ip1);
-      dL = minmod2(d_im1, d_i);
-    }
-    // Eqs. upper_limiter, median_value, large_curvature (alpha 1.25)
-    const double ul = 1.25 * dm;
-    const double md = fma(0.5, dp, -0.5 * dR);
-    const double lc = fma(tp.mp_beta3, dL, 0.5 * dm);
-    // Eq. value_min_max; 0 (= f_i) lies in both brackets, so lo <= 0 <= hi
-    lo = fmax(fmin(fmin(0.0, dp), md), fmin(fmin(0.0, ul), lc));
-    hi = fmin(fmax(fmax(0.0, dp), md), fmax(fmax(0.0, ul), lc));
+    MpState ms;
+    mp_bounds<K, LIM>(D, tp, ms);
+    lo = ms.lo;
+    hi = ms.hi;
   } else if constexpr (LIM == LIM_TVD_MINMOD) {
     ftvd = 0.5 * minmod2(dm, dp);
   } else if constexpr (LIM == LIM_TVD5) {
-    // Eqs. high order TVD, TVDhighorder2, TVDbeta multiplied through by
-    // delta^- (division-free; equal wherever the slope ratios exist)
-    const double B = fma(-3.0, D[C0 + 1], fma(24.0, dp, fma(11.0, dm, -2.0 * D[C0 - 2]))) * (1.0 / 30.0);
+    const double B = tvd5_b<K>(D);
     const double up = fmax(0.0, fmin(fmin(2.0 * dm, 2.0 * dp), B));
     const double dn = fmin(0.0, fmax(fmax(2.0 * dm, 2.0 * dp), B));
     ftvd = 0.5 * (dm > 0.0 ? up : (dm < 0.0 ? dn : 0.0));
   } else if constexpr (LIM == LIM_VA) {
-    // Eqs. van_Albada_limiter, slop_ratio, vAflux with kappa = 1/3:
-    // phi = 2 r/(r^2 + 1) = 2 d+ d- / (d+^2 + d-^2), 0 when both vanish.
-    // Branch-free: the denominator is raised to the smallest normal, which
-    // changes nothing unless |d+|, |d-| < 1e-154, and gives 0 * finite = 0
-    // when both differences vanish.
-    const double den = fmax(fma(dp, dp, dm * dm), 2.2250738585072014e-308);
-    const double phi = 2.0 * dp * dm * rcp(den);
+    const double phi = 2.0 * dp * dm * rcp(va_den(dm, dp));
     const double kp = phi * (1.0 / 3.0);
     ftvd = 0.25 * phi * fma(1.0 - kp, dm, (1.0 + kp) * dp);
   }
@@ -181,10 +235,9 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
     double num = 0.0, den = 0.0;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const bool smooth = !(g[k] < thr);
-      num = smooth ? fma(T::d(k), c[k], num) : num;
-      den = smooth ? den + T::d(k) : den;
-      if constexpr (FLAGS) bits |= (smooth ? 1u : 0u) << k;
+      num = smooth[k] ? fma(T::d(k), c[k], num) : num;
+      den = smooth[k] ? den + T::d(k) : den;
+      if constexpr (FLAGS) bits |= (smooth[k] ? 1u : 0u) << k;
     }
     return fma(num, rcp(den), v[C0]);
   } else {
@@ -192,15 +245,14 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const bool smooth = !(g[k] < thr);
       double lim;
       if constexpr (LIM == LIM_MP || LIM == LIM_MP_MM) {
         lim = fmin(fmax(c[k], lo), hi);  // median(f_k, f_min, f_max), lo <= hi
       } else {
         lim = ftvd;
       }
-      acc = fma(T::d(k), smooth ? c[k] : lim, acc);
-      if constexpr (FLAGS) bits |= (smooth ? 1u : 0u) << k;
+      acc = fma(T::d(k), smooth[k] ? c[k] : lim, acc);
+      if constexpr (FLAGS) bits |= (smooth[k] ? 1u : 0u) << k;
     }
     return v[C0] + acc;
   }

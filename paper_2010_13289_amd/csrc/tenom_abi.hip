@@ -15,6 +15,7 @@
 #include "../../include/tenom.h"
 #include "abi_common.h"
 #include "dispatch.h"
+#include "vjp_dispatch.h"
 
 using namespace tenom;
 
@@ -124,6 +125,87 @@ bool pick(int nf, int K, FacesFn* f, SweepFn* s) {
   TENOM_CASE(5, 8)
 #undef TENOM_CASE
   return false;
+}
+
+using VjpFn = hipError_t (*)(int, int, const VjpLaunch&);
+
+VjpFn pick_vjp(int nf, int K) {
+#define TENOM_VCASE(NF, KK) \
+  if (nf == NF && K == KK) return tenom_vjp_nf##NF##_k##KK;
+  TENOM_VCASE(1, 6)
+  TENOM_VCASE(1, 8)
+  TENOM_VCASE(3, 6)
+  TENOM_VCASE(3, 8)
+  TENOM_VCASE(4, 6)
+  TENOM_VCASE(4, 8)
+  TENOM_VCASE(5, 6)
+  TENOM_VCASE(5, 8)
+#undef TENOM_VCASE
+  return nullptr;
+}
+
+// faces of `axis` in the adjoint (n + 1 transmissive, n periodic)
+long vjp_faces(const tenom_grid* g, int axis) {
+  const Dims d = dims(g);
+  const long n = axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
+  return d.N / n * (n + (g->bc[axis] == TENOM_BC_TRANSMISSIVE ? 1 : 0));
+}
+
+// out = (acc ? out : 0) + scale * sum over axes of J_axis^T Lbar
+int vjp_axes(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma, const double* U,
+             const double* Lbar, double scale, double* out, bool acc, double* contrib, hipStream_t s) {
+  bool adaptive;
+  const int K = scheme_K(scheme, &adaptive);
+  int kind;
+  double beta;
+  limiter_kind(limiter, &kind, &beta);
+  VjpFn fn = pick_vjp(nfields(g), K);
+  if (!fn) return fail(TENOM_EUNSUPPORTED, "no adjoint kernel for %d fields, K = %d", nfields(g), K);
+  const Dims d = dims(g);
+  for (int ax = 0; ax < g->ndim; ++ax) {
+    VjpLaunch L;
+    L.U = U;
+    L.Lbar = Lbar;
+    L.contrib = contrib;
+    L.out = out;
+    L.scale = scale;
+    L.acc = (acc || ax > 0) ? 1 : 0;
+    L.ax.nx = d.nx;
+    L.ax.ny = d.ny;
+    L.ax.nz = d.nz;
+    L.ax.axis = ax;
+    L.ax.bc = g->bc[ax];
+    L.ax.n = ax == 0 ? d.nx : (ax == 1 ? d.ny : d.nz);
+    L.ax.nfa = L.ax.n + (g->bc[ax] == TENOM_BC_TRANSMISSIVE ? 1 : 0);
+    L.ax.nfaces = vjp_faces(g, ax);
+    L.ax.inv_dx = 1.0 / g->dx[ax];
+    field_map(g, ax, L.fld);
+    L.fp = face_params(g, ax, limiter, C_T, gamma);
+    L.stream = s;
+    hipError_t e;
+    {
+      ProfScope ps(7, s);
+      e = fn(kind, adaptive ? 1 : 0, L);
+    }
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+  }
+  return TENOM_OK;
+}
+
+// out = a x + b y (y may be NULL), elementwise over M values
+__global__ __launch_bounds__(256) void k_axpby(double* __restrict__ out, double a, const double* x, double b,
+                                               const double* y, long M) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (long)gridDim.x * blockDim.x)
+    out[i] = y ? fma(a, x[i], b * y[i]) : a * x[i];
+}
+
+int axpby(double* out, double a, const double* x, double b, const double* y, long M, hipStream_t s) {
+  long blocks = (M + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)blocks), dim3(256), 0, s, out, a, x, b, y, M);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TENOM_OK : hip_fail(e, "axpby launch");
 }
 
 int march_segment(int n, int nx, int n_other) {
@@ -435,6 +517,88 @@ int tenom_check_finite(const tenom_grid* grid, const double* U, void* stream) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "finiteness readback");
   return h ? fail(TENOM_ENONFINITE, "state holds NaN or Inf") : TENOM_OK;
+}
+
+size_t tenom_vjp_workspace_bytes(const tenom_grid* grid, int scheme) {
+  bool adaptive;
+  const int K = scheme_K(scheme, &adaptive);
+  if (!K || check_grid(grid, K) != TENOM_OK) return 0;
+  long faces = 0;
+  for (int ax = 0; ax < grid->ndim; ++ax) {
+    const long f = vjp_faces(grid, ax);
+    faces = f > faces ? f : faces;
+  }
+  return align256((size_t)K * (size_t)nfields(grid) * (size_t)faces * sizeof(double));
+}
+
+int tenom_flux_divergence_vjp(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma,
+                              const double* U, const double* Lbar, double scale, double* Ubar, int accumulate,
+                              void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_scheme(grid, scheme, limiter, C_T, gamma);
+  if (rc) return rc;
+  if (!U || !Lbar || !Ubar || !ws) return fail(TENOM_EINVAL, "U, Lbar, Ubar and ws must not be NULL");
+  if ((const void*)Ubar == (const void*)U || (const void*)Ubar == (const void*)Lbar)
+    return fail(TENOM_EINVAL, "Ubar must not alias U or Lbar");
+  if (!isfinite(scale)) return fail(TENOM_EINVAL, "scale must be finite");
+  const size_t need = tenom_vjp_workspace_bytes(grid, scheme);
+  if (ws_bytes < need) return fail(TENOM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return vjp_axes(grid, scheme, limiter, C_T, gamma, U, Lbar, scale, Ubar, accumulate != 0, (double*)ws,
+                  (hipStream_t)stream);
+}
+
+size_t tenom_rk3_vjp_workspace_bytes(const tenom_grid* grid, int scheme) {
+  const size_t contrib = tenom_vjp_workspace_bytes(grid, scheme);
+  if (!contrib) return 0;
+  const size_t state = align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
+  return 5 * state + contrib;  // R, U1, U2, Ubar1, Ubar2, face contributions
+}
+
+int tenom_rk3_step_vjp(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                       const double* U, double* Ubar, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  int rc = check_scheme(grid, scheme, limiter, C_T, gamma);
+  if (rc) return rc;
+  if (!U || !Ubar || !ws) return fail(TENOM_EINVAL, "U, Ubar and ws must not be NULL");
+  if ((const void*)U == (const void*)Ubar) return fail(TENOM_EINVAL, "Ubar must not alias U");
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(TENOM_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+  if (((uintptr_t)ws & 255) != 0) return fail(TENOM_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = tenom_rk3_vjp_workspace_bytes(grid, scheme);
+  if (ws_bytes < need) return fail(TENOM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  const size_t state = align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
+  double* R = (double*)ws;
+  double* U1 = (double*)((char*)ws + state);
+  double* U2 = (double*)((char*)ws + 2 * state);
+  double* B1 = (double*)((char*)ws + 3 * state);
+  double* B2 = (double*)((char*)ws + 4 * state);
+  double* contrib = (double*)((char*)ws + 5 * state);
+  hipStream_t s = (hipStream_t)stream;
+  const int nd = grid->ndim;
+  const long M = (long)nfields(grid) * dims(grid).N;
+  // the stage states of the forward step, by the same sweeps as tenom_rk3_step
+  const double A[2] = {0.0, 0.75};
+  const double B[2] = {1.0, 0.25};
+  const double* Uin[2] = {U, U1};
+  double* Uo[2] = {U1, U2};
+  for (int st = 0; st < 2; ++st) {
+    for (int ax = 0; ax < nd; ++ax) {
+      const bool last = (ax == nd - 1);
+      int mode = last ? (nd == 1 ? EPI_RK1 : EPI_RK) : (ax == 0 ? EPI_STORE : EPI_ACCUM);
+      rc = sweep(grid, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uo[st], A[st], B[st], dt, mode, s);
+      if (rc) return rc;
+    }
+  }
+  // U3 = U/3 + 2/3 (U2 + dt L(U2)):  Ubar2 = 2/3 Ubar3 + 2/3 dt J(U2)^T Ubar3, Ubar_n = Ubar3 / 3
+  if ((rc = axpby(B2, 2.0 / 3.0, Ubar, 0.0, nullptr, M, s))) return rc;
+  if ((rc = vjp_axes(grid, scheme, limiter, C_T, gamma, U2, Ubar, 2.0 / 3.0 * dt, B2, true, contrib, s))) return rc;
+  if ((rc = axpby(Ubar, 1.0 / 3.0, Ubar, 0.0, nullptr, M, s))) return rc;
+  // U2 = 3/4 U + 1/4 (U1 + dt L(U1)):  Ubar1 = 1/4 Ubar2 + 1/4 dt J(U1)^T Ubar2, Ubar_n += 3/4 Ubar2
+  if ((rc = axpby(B1, 0.25, B2, 0.0, nullptr, M, s))) return rc;
+  if ((rc = vjp_axes(grid, scheme, limiter, C_T, gamma, U1, B2, 0.25 * dt, B1, true, contrib, s))) return rc;
+  if ((rc = axpby(Ubar, 0.75, B2, 1.0, Ubar, M, s))) return rc;
+  // U1 = U + dt L(U):  Ubar_n += Ubar1 + dt J(U)^T Ubar1
+  if ((rc = axpby(Ubar, 1.0, B1, 1.0, Ubar, M, s))) return rc;
+  return vjp_axes(grid, scheme, limiter, C_T, gamma, U, B1, dt, Ubar, true, contrib, s);
 }
 
 int tenom_profile_enable(int on) {
