@@ -13,9 +13,11 @@
 // and nowhere otherwise; alpha takes the first maximising cell; |u_n| in
 // the signal speed passes sgn(u_n), 0 at u_n = 0.
 //
-//  k_faces_vjp   one thread per face of one axis: recompute the face and
-//                push the face cotangent (from the cotangent of dU/dt) back
-//                to the K x NF stencil inputs, written per face and slot.
+//  k_faces_vjp_euler  one wavefront per (64 faces, characteristic field) of
+//                one axis: recompute the face and push the face cotangent
+//                (from the cotangent of dU/dt) back to the K x NF stencil
+//                inputs, written per face and slot (k_faces_vjp_scalar: one
+//                thread per face of the scalar system).
 //  k_gather_vjp  one thread per cell: sum the contributions of the faces
 //                whose stencils hold the cell, in a fixed order (no atomics).
 #pragma once
@@ -108,9 +110,11 @@ __device__ __forceinline__ void mp_bounds_vjp(const double (&D)[K - 1], const Te
 
 // Adjoint of one TENO-M reconstruction: vbar += rbar * (d r / d v) with the
 // decisions of teno_m on the same v.
-template <int K, int LIM, bool ADAPT>
-__device__ __forceinline__ void teno_m_vjp(const double (&v)[K], const TenoParams& tp, double rbar,
-                                           double (&vbar)[K]) {
+// The decisions are passed in (bit k of `mask` set = candidate k smooth),
+// as taken by teno_m on the same v.
+template <int K, int LIM>
+__device__ __forceinline__ void teno_m_vjp_given(const double (&v)[K], const TenoParams& tp, uint32_t mask,
+                                                 double rbar, double (&vbar)[K]) {
   using T = TenoTables<K>;
   constexpr int NK = K - 2;
   constexpr int C0 = K / 2 - 1;
@@ -118,7 +122,8 @@ __device__ __forceinline__ void teno_m_vjp(const double (&v)[K], const TenoParam
 #pragma unroll
   for (int j = 0; j < K - 1; ++j) D[j] = v[j + 1] - v[j];
   bool smooth[NK];
-  teno_cutoff<K, ADAPT>(D, tp, smooth);
+#pragma unroll
+  for (int k = 0; k < NK; ++k) smooth[k] = (mask >> k) & 1u;
   double cbar[NK];
   double Dbar[K - 1];
 #pragma unroll
@@ -222,6 +227,20 @@ __device__ __forceinline__ void teno_m_vjp(const double (&v)[K], const TenoParam
   }
 }
 
+template <int K, int LIM, bool ADAPT>
+__device__ __forceinline__ void teno_m_vjp(const double (&v)[K], const TenoParams& tp, double rbar,
+                                           double (&vbar)[K]) {
+  double D[K - 1];
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) D[j] = v[j + 1] - v[j];
+  bool smooth[K - 2];
+  teno_cutoff<K, ADAPT>(D, tp, smooth);
+  uint32_t mask = 0;
+#pragma unroll
+  for (int k = 0; k < K - 2; ++k) mask |= (smooth[k] ? 1u : 0u) << k;
+  teno_m_vjp_given<K, LIM>(v, tp, mask, rbar, vbar);
+}
+
 // ---------------------------------------------------------------------------
 // reverse of the per-cell physics
 // ---------------------------------------------------------------------------
@@ -295,192 +314,241 @@ __device__ __forceinline__ void roe_input_vjp(const double (&X)[NF], double gamm
 }
 
 // ---------------------------------------------------------------------------
-// reverse of one Euler face: X[m][q] = rotated state of window cell m,
-// Fhbar = cotangent of the face flux (rotated components); Xbar accumulates.
+// One Euler face, split by characteristic field.  FaceState holds what all
+// fields share (alpha and its maximiser, the Roe average and the
+// eigenvector constants), computed exactly as the forward face does;
+// FaceBars collects the cotangents of those shared values.
 // ---------------------------------------------------------------------------
-template <int NF, int K, int LIM, bool ADAPT>
-__device__ __forceinline__ void euler_face_vjp(const double (&X)[K][NF], double gamma, const TenoParams& tp,
-                                               const double (&Fhbar)[NF], double (&Xbar)[K][NF]) {
+template <int NF>
+struct FaceState {
+  double alpha;
+  int mstar;
+  RoeIn<NF> ra, rb;
+  double w;  // 1 / (sqrt(rho_a) + sqrt(rho_b))
+  double ut[NF - 2], Ht, q2, ct, cinv, b1, b2;
+};
+
+template <int NF>
+struct FaceBars {
+  double ut[NF - 2], b1, b2, cinv, ct, Ht, q2;
+};
+
+template <int NF, int K>
+__device__ __forceinline__ void face_state(const double (&X)[K][NF], double gamma, FaceState<NF>& s) {
   constexpr int ND = NF - 2;
   constexpr int H = K / 2;
   const double gm1 = gamma - 1.0;
-  // ---- forward recomputation
-  double F[K][NF], lam[K];
-  double alpha = 0.0;
-  int mstar = 0;
+  s.alpha = 0.0;
+  s.mstar = 0;
 #pragma unroll
   for (int m = 0; m < K; ++m) {
-    cell_physics<NF>(X[m], gamma, F[m], lam[m]);
-    if (!(alpha >= lam[m])) {  // alpha = fmax(alpha, lam): the first maximum
-      alpha = lam[m];
-      mstar = m;
+    double Fm[NF], lam;
+    cell_physics<NF>(X[m], gamma, Fm, lam);
+    if (!(s.alpha >= lam)) {  // alpha = fmax(alpha, lam): the first maximum
+      s.alpha = lam;
+      s.mstar = m;
     }
   }
-  RoeIn<NF> ra, rb;
-  roe_input<NF>(X[H - 1], gamma, ra);
-  roe_input<NF>(X[H], gamma, rb);
-  const double wsum = ra.rs + rb.rs;
-  const double w = rcp(wsum);
-  double ut[ND];
+  roe_input<NF>(X[H - 1], gamma, s.ra);
+  roe_input<NF>(X[H], gamma, s.rb);
+  s.w = rcp(s.ra.rs + s.rb.rs);
 #pragma unroll
-  for (int d = 0; d < ND; ++d) ut[d] = fma(ra.rs, ra.u[d], rb.rs * rb.u[d]) * w;
-  const double Ht = fma(ra.rs, ra.H, rb.rs * rb.H) * w;
-  double q2 = 0.0;
+  for (int d = 0; d < ND; ++d) s.ut[d] = fma(s.ra.rs, s.ra.u[d], s.rb.rs * s.rb.u[d]) * s.w;
+  s.Ht = fma(s.ra.rs, s.ra.H, s.rb.rs * s.rb.H) * s.w;
+  s.q2 = 0.0;
 #pragma unroll
-  for (int d = 0; d < ND; ++d) q2 = fma(ut[d], ut[d], q2);
-  const double cs = fma(-0.5, q2, Ht);
-  const double ct = sqrt(gm1 * cs);
-  const double cinv = rcp(ct);
-  const double b1 = gm1 * cinv * cinv;
-  const double b2 = 0.5 * q2 * b1;
-  auto project = [&](const double (&Y)[NF], double (&o)[NF]) {
+  for (int d = 0; d < ND; ++d) s.q2 = fma(s.ut[d], s.ut[d], s.q2);
+  s.ct = sqrt(gm1 * fma(-0.5, s.q2, s.Ht));
+  s.cinv = rcp(s.ct);
+  s.b1 = gm1 * s.cinv * s.cinv;
+  s.b2 = 0.5 * s.q2 * s.b1;
+}
+
+// Component Q of the left-eigenvector projection (the expressions of the
+// forward face, so the values are the same bits).
+template <int NF, int Q>
+__device__ __forceinline__ double project_row(const FaceState<NF>& s, const double (&Y)[NF]) {
+  constexpr int ND = NF - 2;
+  if constexpr (Q == 0 || Q == 1 || Q == NF - 1) {
     double um = 0.0;
 #pragma unroll
-    for (int d = 0; d < ND; ++d) um = fma(ut[d], Y[1 + d], um);
-    const double A = fma(b2, Y[0], b1 * (Y[NF - 1] - um));
-    const double Bn = fma(ut[0], Y[0], -Y[1]);
-    o[0] = 0.5 * fma(Bn, cinv, A);
-    o[1] = Y[0] - A;
-#pragma unroll
-    for (int t = 1; t < ND; ++t) o[1 + t] = fma(-ut[t], Y[0], Y[1 + t]);
-    o[NF - 1] = 0.5 * fma(-Bn, cinv, A);
-  };
-  double W[K][NF], G[K][NF];
-#pragma unroll
-  for (int m = 0; m < K; ++m) {
-    project(X[m], W[m]);
-    project(F[m], G[m]);
-  }
-  double fc[NF];
-#pragma unroll
-  for (int q = 0; q < NF; ++q) {
-    double vp[K], vm[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) lf_split2(G[m][q], alpha, W[m][q], vp[m], vm[K - 1 - m]);
-    uint32_t b0 = 0, b1u = 0;
-    fc[q] = 0.5 * (teno_m<K, LIM, false, ADAPT>(vp, tp, b0) + teno_m<K, LIM, false, ADAPT>(vm, tp, b1u));
-  }
-  // ---- reverse of the back-projection F = R fc
-  double fcbar[NF], utbar[ND];
-#pragma unroll
-  for (int q = 0; q < NF; ++q) fcbar[q] = 0.0;
-#pragma unroll
-  for (int d = 0; d < ND; ++d) utbar[d] = 0.0;
-  double ctbar = 0.0, Htbar = 0.0, q2bar = 0.0;
-  {
-    const double s = fc[0] + fc[1] + fc[NF - 1];
-    const double dlr = fc[NF - 1] - fc[0];
-    const double ebar = Fhbar[NF - 1];
-    double sbar = Fhbar[0] + Fhbar[1] * ut[0];
-    double dlrbar = Fhbar[1] * ct + ebar * ut[0] * ct;
-    utbar[0] += Fhbar[1] * s + ebar * ct * dlr;
-    ctbar += Fhbar[1] * dlr + ebar * ut[0] * dlr;
-    Htbar += ebar * (fc[0] + fc[NF - 1]);
-    fcbar[0] += ebar * Ht;
-    fcbar[NF - 1] += ebar * Ht;
-    fcbar[1] += ebar * 0.5 * q2;
-    q2bar += ebar * 0.5 * fc[1];
-#pragma unroll
-    for (int t = 1; t < ND; ++t) {
-      sbar += Fhbar[1 + t] * ut[t];
-      utbar[t] += Fhbar[1 + t] * s + ebar * fc[1 + t];
-      fcbar[1 + t] += Fhbar[1 + t] + ebar * ut[t];
+    for (int d = 0; d < ND; ++d) um = fma(s.ut[d], Y[1 + d], um);
+    const double A = fma(s.b2, Y[0], s.b1 * (Y[NF - 1] - um));
+    if constexpr (Q == 1) {
+      return Y[0] - A;
+    } else {
+      const double Bn = fma(s.ut[0], Y[0], -Y[1]);
+      return Q == 0 ? 0.5 * fma(Bn, s.cinv, A) : 0.5 * fma(-Bn, s.cinv, A);
     }
-    fcbar[0] += sbar - dlrbar;
-    fcbar[1] += sbar;
-    fcbar[NF - 1] += sbar + dlrbar;
+  } else {
+    return fma(-s.ut[Q - 1], Y[0], Y[Q]);
   }
-  // ---- reverse of the reconstructions and the split; W, G become their cotangents
-  double alphabar = 0.0;
-#pragma unroll
-  for (int q = 0; q < NF; ++q) {
-    double vp[K], vm[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) lf_split2(G[m][q], alpha, W[m][q], vp[m], vm[K - 1 - m]);
-    double vpbar[K], vmbar[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) vpbar[m] = vmbar[m] = 0.0;
-    teno_m_vjp<K, LIM, ADAPT>(vp, tp, 0.5 * fcbar[q], vpbar);
-    teno_m_vjp<K, LIM, ADAPT>(vm, tp, 0.5 * fcbar[q], vmbar);
-#pragma unroll
-    for (int m = 0; m < K; ++m) {
-      // vp[m] = G + alpha W, vm[K-1-m] = G - alpha W
-      const double pb = vpbar[m], mb = vmbar[K - 1 - m];
-      alphabar += W[m][q] * (pb - mb);
-      G[m][q] = pb + mb;
-      W[m][q] = alpha * (pb - mb);
-    }
-  }
-  // ---- reverse of the projections: o = L(ut, b1, b2, cinv) Y
-  double b1bar = 0.0, b2bar = 0.0, cinvbar = 0.0;
-  double Fbar[K][NF];
-  auto project_vjp = [&](const double (&Y)[NF], const double (&ob)[NF], double (&Yb)[NF]) {
+}
+
+// Adjoint of project_row: ob -> Yb and the shared cotangents.
+template <int NF, int Q>
+__device__ __forceinline__ void project_row_vjp(const FaceState<NF>& s, const double (&Y)[NF], double ob,
+                                                double (&Yb)[NF], FaceBars<NF>& b) {
+  constexpr int ND = NF - 2;
+  if constexpr (Q == 0 || Q == 1 || Q == NF - 1) {
     double um = 0.0;
 #pragma unroll
-    for (int d = 0; d < ND; ++d) um = fma(ut[d], Y[1 + d], um);
-    const double Bn = fma(ut[0], Y[0], -Y[1]);
-    const double Abar = 0.5 * ob[0] - ob[1] + 0.5 * ob[NF - 1];
-    const double Bnbar = 0.5 * cinv * (ob[0] - ob[NF - 1]);
-    cinvbar += 0.5 * Bn * (ob[0] - ob[NF - 1]);
+    for (int d = 0; d < ND; ++d) um = fma(s.ut[d], Y[1 + d], um);
+    double Abar;
+    if constexpr (Q == 1) {
+      Yb[0] += ob;
+      Abar = -ob;
+    } else {
+      const double Bn = fma(s.ut[0], Y[0], -Y[1]);
+      const double sg = (Q == 0) ? 0.5 : -0.5;
+      Abar = 0.5 * ob;
+      const double Bnbar = sg * s.cinv * ob;
+      b.cinv += sg * Bn * ob;
+      b.ut[0] += Bnbar * Y[0];
+      Yb[0] += Bnbar * s.ut[0];
+      Yb[1] -= Bnbar;
+    }
     // A = b2 Y0 + b1 (Y_E - um)
-    b2bar += Abar * Y[0];
-    b1bar += Abar * (Y[NF - 1] - um);
-    Yb[0] += Abar * b2 + ob[1] + Bnbar * ut[0];
-    Yb[NF - 1] += Abar * b1;
-    const double umbar = -Abar * b1;
-    // Bn = ut0 Y0 - Y1
-    utbar[0] += Bnbar * Y[0];
-    Yb[1] -= Bnbar;
-#pragma unroll
-    for (int t = 1; t < ND; ++t) {
-      // o_{1+t} = Y_{1+t} - ut_t Y0
-      Yb[1 + t] += ob[1 + t];
-      Yb[0] -= ob[1 + t] * ut[t];
-      utbar[t] -= ob[1 + t] * Y[0];
-    }
+    b.b2 += Abar * Y[0];
+    Yb[0] += Abar * s.b2;
+    b.b1 += Abar * (Y[NF - 1] - um);
+    Yb[NF - 1] += Abar * s.b1;
+    const double umbar = -Abar * s.b1;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-      utbar[d] += umbar * Y[1 + d];
-      Yb[1 + d] += umbar * ut[d];
+      b.ut[d] += umbar * Y[1 + d];
+      Yb[1 + d] += umbar * s.ut[d];
     }
-  };
+  } else {
+    Yb[0] -= s.ut[Q - 1] * ob;
+    Yb[Q] += ob;
+    b.ut[Q - 1] -= Y[0] * ob;
+  }
+}
+
+// Per-field intermediates the forward pass keeps for the adjoint.
+template <int K>
+struct FieldKeep {
+  double vp[K], vm[K];  // doubled split values (vm mirrored)
+  double W[K], G[K];    // row Q of the projections of U and F
+  uint32_t mp, mm;      // smoothness decisions of the two reconstructions
+};
+
+// Field Q of the forward face: fc_Q = (TENO(g+) + TENO(g-)) / 2 (doubled split).
+template <int NF, int K, int LIM, bool ADAPT, int Q>
+__device__ __forceinline__ double field_forward(const double (&X)[K][NF], const FaceState<NF>& s, double gamma,
+                                                const TenoParams& tp, FieldKeep<K>& f) {
 #pragma unroll
   for (int m = 0; m < K; ++m) {
-#pragma unroll
-    for (int q = 0; q < NF; ++q) Fbar[m][q] = 0.0;
-    project_vjp(X[m], W[m], Xbar[m]);
-    project_vjp(F[m], G[m], Fbar[m]);
+    double Fm[NF], lam;
+    cell_physics<NF>(X[m], gamma, Fm, lam);
+    f.W[m] = project_row<NF, Q>(s, X[m]);
+    f.G[m] = project_row<NF, Q>(s, Fm);
+    lf_split2(f.G[m], s.alpha, f.W[m], f.vp[m], f.vm[K - 1 - m]);
   }
-  // ---- reverse of the cell fluxes and of alpha (at its first maximiser)
+  f.mp = f.mm = 0u;
+  return 0.5 * (teno_m<K, LIM, true, ADAPT>(f.vp, tp, f.mp) + teno_m<K, LIM, true, ADAPT>(f.vm, tp, f.mm));
+}
+
+// Adjoint of field Q: fcbar_Q -> Xbar (through the reconstructions, the
+// split, row Q of both projections, the cell fluxes and alpha) and the
+// shared cotangents.
+template <int NF, int K, int LIM, int Q>
+__device__ __forceinline__ void field_vjp(const double (&X)[K][NF], const FaceState<NF>& s, double gamma,
+                                          const TenoParams& tp, double fcbar, FieldKeep<K>& f,
+                                          double (&Xbar)[K][NF], FaceBars<NF>& b) {
+  double vpbar[K], vmbar[K];
 #pragma unroll
-  for (int m = 0; m < K; ++m) cell_physics_vjp<NF>(X[m], gamma, Fbar[m], m == mstar ? alphabar : 0.0, Xbar[m]);
-  // ---- reverse of the eigenvector constants and the Roe average
+  for (int m = 0; m < K; ++m) vpbar[m] = vmbar[m] = 0.0;
+  teno_m_vjp_given<K, LIM>(f.vp, tp, f.mp, 0.5 * fcbar, vpbar);
+  teno_m_vjp_given<K, LIM>(f.vm, tp, f.mm, 0.5 * fcbar, vmbar);
+  double alphabar = 0.0;
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    // vp[m] = G + alpha W, vm[K-1-m] = G - alpha W
+    const double pb = vpbar[m], mb = vmbar[K - 1 - m];
+    alphabar += f.W[m] * (pb - mb);
+    f.G[m] = pb + mb;
+    f.W[m] = s.alpha * (pb - mb);
+  }
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    project_row_vjp<NF, Q>(s, X[m], f.W[m], Xbar[m], b);
+    double Fm[NF], lam, Fb[NF];
+    cell_physics<NF>(X[m], gamma, Fm, lam);
+#pragma unroll
+    for (int r = 0; r < NF; ++r) Fb[r] = 0.0;
+    project_row_vjp<NF, Q>(s, Fm, f.G[m], Fb, b);
+    cell_physics_vjp<NF>(X[m], gamma, Fb, m == s.mstar ? alphabar : 0.0, Xbar[m]);
+  }
+}
+
+// Adjoint of the back-projection F = R fc: Fhbar -> fcbar, and the shared
+// cotangents (added only when `shared`).
+template <int NF>
+__device__ __forceinline__ void backproj_vjp(const FaceState<NF>& s, const double (&fc)[NF], const double (&Fhbar)[NF],
+                                             double (&fcbar)[NF], FaceBars<NF>& b, bool shared) {
+  constexpr int ND = NF - 2;
+  const double sum = fc[0] + fc[1] + fc[NF - 1];
+  const double dlr = fc[NF - 1] - fc[0];
+  const double ebar = Fhbar[NF - 1];
+  double sbar = Fhbar[0] + Fhbar[1] * s.ut[0];
+  const double dlrbar = Fhbar[1] * s.ct + ebar * s.ut[0] * s.ct;
+#pragma unroll
+  for (int q = 0; q < NF; ++q) fcbar[q] = 0.0;
+  fcbar[0] += ebar * s.Ht;
+  fcbar[NF - 1] += ebar * s.Ht;
+  fcbar[1] += ebar * 0.5 * s.q2;
+#pragma unroll
+  for (int t = 1; t < ND; ++t) {
+    sbar += Fhbar[1 + t] * s.ut[t];
+    fcbar[1 + t] += Fhbar[1 + t] + ebar * s.ut[t];
+  }
+  fcbar[0] += sbar - dlrbar;
+  fcbar[1] += sbar;
+  fcbar[NF - 1] += sbar + dlrbar;
+  if (shared) {
+    b.ut[0] += Fhbar[1] * sum + ebar * s.ct * dlr;
+    b.ct += Fhbar[1] * dlr + ebar * s.ut[0] * dlr;
+    b.Ht += ebar * (fc[0] + fc[NF - 1]);
+    b.q2 += ebar * 0.5 * fc[1];
+#pragma unroll
+    for (int t = 1; t < ND; ++t) b.ut[t] += Fhbar[1 + t] * sum + ebar * fc[1 + t];
+  }
+}
+
+// Shared cotangents -> Xbar: eigenvector constants, Roe average, Roe inputs.
+template <int NF, int K>
+__device__ __forceinline__ void shared_vjp(const double (&X)[K][NF], const FaceState<NF>& s, double gamma,
+                                           FaceBars<NF> b, double (&Xbar)[K][NF]) {
+  constexpr int ND = NF - 2;
+  constexpr int H = K / 2;
+  const double gm1 = gamma - 1.0;
   // b2 = q2 b1 / 2, b1 = (gamma-1) cinv^2, cinv = 1/ct, ct = sqrt((gamma-1)(Ht - q2/2))
-  q2bar += 0.5 * b1 * b2bar;
-  b1bar += 0.5 * q2 * b2bar;
-  cinvbar += 2.0 * gm1 * cinv * b1bar;
-  ctbar -= cinv * cinv * cinvbar;
+  b.q2 += 0.5 * s.b1 * b.b2;
+  b.b1 += 0.5 * s.q2 * b.b2;
+  b.cinv += 2.0 * gm1 * s.cinv * b.b1;
+  b.ct -= s.cinv * s.cinv * b.cinv;
   {
-    const double k = gm1 * 0.5 * cinv * ctbar;  // d ct / d cs times ctbar
-    Htbar += k;
-    q2bar -= 0.5 * k;
+    const double k = gm1 * 0.5 * s.cinv * b.ct;
+    b.Ht += k;
+    b.q2 -= 0.5 * k;
   }
 #pragma unroll
-  for (int d = 0; d < ND; ++d) utbar[d] += 2.0 * ut[d] * q2bar;
-  // ut = (rs_a u_a + rs_b u_b) w, Ht = (rs_a H_a + rs_b H_b) w, w = 1 / (rs_a + rs_b)
+  for (int d = 0; d < ND; ++d) b.ut[d] += 2.0 * s.ut[d] * b.q2;
+  // ut = (rs_a u_a + rs_b u_b) w, Ht = (rs_a H_a + rs_b H_b) w
   double rsabar = 0.0, rsbbar = 0.0, uabar[ND], ubbar[ND];
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    uabar[d] = utbar[d] * ra.rs * w;
-    ubbar[d] = utbar[d] * rb.rs * w;
-    rsabar += utbar[d] * (ra.u[d] - ut[d]) * w;
-    rsbbar += utbar[d] * (rb.u[d] - ut[d]) * w;
+    uabar[d] = b.ut[d] * s.ra.rs * s.w;
+    ubbar[d] = b.ut[d] * s.rb.rs * s.w;
+    rsabar += b.ut[d] * (s.ra.u[d] - s.ut[d]) * s.w;
+    rsbbar += b.ut[d] * (s.rb.u[d] - s.ut[d]) * s.w;
   }
-  const double Habar = Htbar * ra.rs * w, Hbbar = Htbar * rb.rs * w;
-  rsabar += Htbar * (ra.H - Ht) * w;
-  rsbbar += Htbar * (rb.H - Ht) * w;
-  roe_input_vjp<NF>(X[H - 1], gamma, rsabar, uabar, Habar, Xbar[H - 1]);
-  roe_input_vjp<NF>(X[H], gamma, rsbbar, ubbar, Hbbar, Xbar[H]);
+  rsabar += b.Ht * (s.ra.H - s.Ht) * s.w;
+  rsbbar += b.Ht * (s.rb.H - s.Ht) * s.w;
+  roe_input_vjp<NF>(X[H - 1], gamma, rsabar, uabar, b.Ht * s.ra.rs * s.w, Xbar[H - 1]);
+  roe_input_vjp<NF>(X[H], gamma, rsbbar, ubbar, b.Ht * s.rb.rs * s.w, Xbar[H]);
 }
 
 // Scalar advection f = a u: Fbar -> ubar.
@@ -533,62 +601,148 @@ __device__ __forceinline__ void vjp_face_line(const VjpAxis& a, long t, Line& L,
   }
 }
 
-// contrib[(m * NF + field) * nfaces + face] = d(Lbar . dU/dt)/dU at stencil slot m
-template <int NF, int K, int LIM, bool ADAPT>
-__global__ __launch_bounds__(256) void k_faces_vjp(const double* __restrict__ U, const double* __restrict__ Lbar,
-                                                   double* __restrict__ contrib, VjpAxis ax, int fld0, int fld1,
-                                                   int fld2, int fld3, int fld4, FaceParams fp) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ax.nfaces) return;
-  Line L;
-  int j;
-  vjp_face_line(ax, t, L, j);
-  const long N = (long)ax.nx * ax.ny * ax.nz;
-  const int fall[5] = {fld0, fld1, fld2, fld3, fld4};
-  int fld[NF];
-#pragma unroll
-  for (int q = 0; q < NF; ++q) fld[q] = fall[q];
-  // face j lies between cells j-1 and j; dU/dt_i = -(F_{i+1} - F_i)/dx, so
-  // Fbar_j = (Lbar_j - Lbar_{j-1}) / dx over the cells that exist
+// Face cotangent from the cotangent of dU/dt: dU/dt_i = -(F_{i+1} - F_i)/dx
+// (face j between cells j-1 and j), so Fbar_j = (Lbar_j - Lbar_{j-1}) / dx
+// over the cells that exist.
+template <int NF>
+__device__ __forceinline__ void face_cotangent(const VjpAxis& ax, const Line& L, int j, long N, const int (&fld)[NF],
+                                               const double* __restrict__ Lbar, double (&Fhbar)[NF]) {
   const bool per = (ax.bc == 0);
   const bool has_r = per || j < ax.n;
   const bool has_l = per || j > 0;
   const long cr = cell_at(L, per ? j : min(j, ax.n - 1));
   const long cl = cell_at(L, j - 1);
-  double Fhbar[NF];
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
     const double r = has_r ? Lbar[(long)fld[q] * N + cr] : 0.0;
     const double l = has_l ? Lbar[(long)fld[q] * N + cl] : 0.0;
     Fhbar[q] = (r - l) * ax.inv_dx;
   }
+}
+
+// Scalar system: one thread per face.
+// contrib[(m * NF + field) * nfaces + face] = d(Lbar . dU/dt)/dU at stencil slot m
+template <int K, int LIM, bool ADAPT>
+__global__ __launch_bounds__(256) void k_faces_vjp_scalar(const double* __restrict__ U,
+                                                          const double* __restrict__ Lbar,
+                                                          double* __restrict__ contrib, VjpAxis ax, FaceParams fp) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ax.nfaces) return;
+  Line L;
+  int j;
+  vjp_face_line(ax, t, L, j);
+  const long N = (long)ax.nx * ax.ny * ax.nz;
+  const int fld[1] = {0};
+  double Fhbar[1];
+  face_cotangent<1>(ax, L, j, N, fld, Lbar, Fhbar);
+  double u[K], ub[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    u[m] = U[cell_at(L, j - K / 2 + m)];
+    ub[m] = 0.0;
+  }
+  scalar_face_vjp<K, LIM, ADAPT>(u, fp.adv, fp.tp, Fhbar[0], ub);
+#pragma unroll
+  for (int m = 0; m < K; ++m) contrib[(long)m * ax.nfaces + t] = ub[m];
+}
+
+// Euler system: a workgroup of NF wavefronts handles 64 faces, wavefront q
+// (threadIdx.y, uniform in the wave) the characteristic field q.  Every wave
+// recomputes the shared face state; the forward field results are exchanged
+// through LDS for the back-projection; each wave pushes its cotangents back
+// to the stencil (the shared ones included: the map is linear in them) and
+// the NF partial stencil cotangents are summed in LDS in the order q = 0,
+// 1, ... .
+template <int NF, int K, int LIM, bool ADAPT>
+__global__ __launch_bounds__(64 * NF) void k_faces_vjp_euler(const double* __restrict__ U,
+                                                             const double* __restrict__ Lbar,
+                                                             double* __restrict__ contrib, VjpAxis ax, int fld0,
+                                                             int fld1, int fld2, int fld3, int fld4, FaceParams fp) {
+  __shared__ double fcs[NF][64];
+  __shared__ double acc[K * NF][64];
+  const int lane = threadIdx.x;
+  const int q = threadIdx.y;
+  const long t = (long)blockIdx.x * 64 + lane;
+  const bool valid = t < ax.nfaces;
+  const long tt = valid ? t : ax.nfaces - 1;  // every thread takes part in the barriers
+  Line L;
+  int j;
+  vjp_face_line(ax, tt, L, j);
+  const long N = (long)ax.nx * ax.ny * ax.nz;
+  const int fall[5] = {fld0, fld1, fld2, fld3, fld4};
+  int fld[NF];
+#pragma unroll
+  for (int r = 0; r < NF; ++r) fld[r] = fall[r];
   double X[K][NF], Xbar[K][NF];
 #pragma unroll
   for (int m = 0; m < K; ++m) {
     const long cell = cell_at(L, j - K / 2 + m);
 #pragma unroll
-    for (int q = 0; q < NF; ++q) {
-      X[m][q] = U[(long)fld[q] * N + cell];
-      Xbar[m][q] = 0.0;
+    for (int r = 0; r < NF; ++r) {
+      X[m][r] = U[(long)fld[r] * N + cell];
+      Xbar[m][r] = 0.0;
     }
   }
-  if constexpr (NF == 1) {
-    double u[K], ub[K];
-#pragma unroll
-    for (int m = 0; m < K; ++m) {
-      u[m] = X[m][0];
-      ub[m] = 0.0;
-    }
-    scalar_face_vjp<K, LIM, ADAPT>(u, fp.adv, fp.tp, Fhbar[0], ub);
-#pragma unroll
-    for (int m = 0; m < K; ++m) Xbar[m][0] = ub[m];
-  } else {
-    euler_face_vjp<NF, K, LIM, ADAPT>(X, fp.gamma, fp.tp, Fhbar, Xbar);
+  FaceState<NF> s;
+  face_state<NF, K>(X, fp.gamma, s);
+  // forward field q (its intermediates kept for the adjoint)
+  FieldKeep<K> keep;
+  double fcq = 0.0;
+  switch (q) {
+    case 0: fcq = field_forward<NF, K, LIM, ADAPT, 0>(X, s, fp.gamma, fp.tp, keep); break;
+    case 1: fcq = field_forward<NF, K, LIM, ADAPT, 1>(X, s, fp.gamma, fp.tp, keep); break;
+    case 2: fcq = field_forward<NF, K, LIM, ADAPT, 2>(X, s, fp.gamma, fp.tp, keep); break;
+    default:
+      if constexpr (NF > 3) {
+        if (q == 3) fcq = field_forward<NF, K, LIM, ADAPT, 3>(X, s, fp.gamma, fp.tp, keep);
+      }
+      if constexpr (NF > 4) {
+        if (q == 4) fcq = field_forward<NF, K, LIM, ADAPT, 4>(X, s, fp.gamma, fp.tp, keep);
+      }
+      break;
   }
+  fcs[q][lane] = fcq;
+  __syncthreads();
+  double fc[NF], Fhbar[NF], fcbar[NF];
 #pragma unroll
-  for (int m = 0; m < K; ++m)
+  for (int r = 0; r < NF; ++r) fc[r] = fcs[r][lane];
+  face_cotangent<NF>(ax, L, j, N, fld, Lbar, Fhbar);
+  FaceBars<NF> b;
 #pragma unroll
-    for (int q = 0; q < NF; ++q) contrib[((long)m * NF + fld[q]) * ax.nfaces + t] = Xbar[m][q];
+  for (int d = 0; d < NF - 2; ++d) b.ut[d] = 0.0;
+  b.b1 = b.b2 = b.cinv = b.ct = b.Ht = b.q2 = 0.0;
+  backproj_vjp<NF>(s, fc, Fhbar, fcbar, b, q == 0);
+  switch (q) {
+    case 0: field_vjp<NF, K, LIM, 0>(X, s, fp.gamma, fp.tp, fcbar[0], keep, Xbar, b); break;
+    case 1: field_vjp<NF, K, LIM, 1>(X, s, fp.gamma, fp.tp, fcbar[1], keep, Xbar, b); break;
+    case 2: field_vjp<NF, K, LIM, 2>(X, s, fp.gamma, fp.tp, fcbar[2], keep, Xbar, b); break;
+    default:
+      if constexpr (NF > 3) {
+        if (q == 3) field_vjp<NF, K, LIM, 3>(X, s, fp.gamma, fp.tp, fcbar[3], keep, Xbar, b);
+      }
+      if constexpr (NF > 4) {
+        if (q == 4) field_vjp<NF, K, LIM, 4>(X, s, fp.gamma, fp.tp, fcbar[4], keep, Xbar, b);
+      }
+      break;
+  }
+  shared_vjp<NF, K>(X, s, fp.gamma, b, Xbar);
+  // sum the partial stencil cotangents over the fields, q = 0, 1, ...
+#pragma unroll 1
+  for (int r = 0; r < NF; ++r) {
+    if (q == r) {
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+#pragma unroll
+        for (int c = 0; c < NF; ++c) acc[m * NF + c][lane] = (r == 0 ? 0.0 : acc[m * NF + c][lane]) + Xbar[m][c];
+    }
+    __syncthreads();
+  }
+  if (valid) {
+    for (int e = q; e < K * NF; e += NF) {
+      const int m = e / NF, c = e - m * NF;
+      contrib[((long)m * NF + fall[c]) * ax.nfaces + t] = acc[e][lane];
+    }
+  }
 }
 
 // out[f][cell] = (acc ? out : 0) + scale * sum of the contributions of every
@@ -667,9 +821,15 @@ struct VjpLaunch {
 
 template <int NF, int K, int LIM, bool ADAPT>
 hipError_t launch_vjp(const VjpLaunch& a) {
-  const unsigned fb = (unsigned)((a.ax.nfaces + 255) / 256);
-  hipLaunchKernelGGL((k_faces_vjp<NF, K, LIM, ADAPT>), dim3(fb), dim3(256), 0, a.stream, a.U, a.Lbar, a.contrib,
-                     a.ax, a.fld[0], a.fld[1], a.fld[2], a.fld[3], a.fld[4], a.fp);
+  if constexpr (NF == 1) {
+    const unsigned fb = (unsigned)((a.ax.nfaces + 255) / 256);
+    hipLaunchKernelGGL((k_faces_vjp_scalar<K, LIM, ADAPT>), dim3(fb), dim3(256), 0, a.stream, a.U, a.Lbar,
+                       a.contrib, a.ax, a.fp);
+  } else {
+    const unsigned fb = (unsigned)((a.ax.nfaces + 63) / 64);
+    hipLaunchKernelGGL((k_faces_vjp_euler<NF, K, LIM, ADAPT>), dim3(fb), dim3(64, NF), 0, a.stream, a.U, a.Lbar,
+                       a.contrib, a.ax, a.fld[0], a.fld[1], a.fld[2], a.fld[3], a.fld[4], a.fp);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long N = (long)a.ax.nx * a.ax.ny * a.ax.nz;
