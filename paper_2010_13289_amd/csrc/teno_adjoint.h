@@ -13,13 +13,15 @@
 // and nowhere otherwise; alpha takes the first maximising cell; |u_n| in
 // the signal speed passes sgn(u_n), 0 at u_n = 0.
 //
-//  k_faces_vjp_euler  one wavefront per (64 faces, characteristic field) of
-//                one axis: recompute the face and push the face cotangent
-//                (from the cotangent of dU/dt) back to the K x NF stencil
-//                inputs, written per face and slot (k_faces_vjp_scalar: one
-//                thread per face of the scalar system).
-//  k_gather_vjp  one thread per cell: sum the contributions of the faces
-//                whose stencils hold the cell, in a fixed order (no atomics).
+//  k_vjp_tile    Euler system: one workgroup per line tile; the tile's cells
+//                are staged in LDS, each thread recomputes one face and
+//                pushes its cotangent (from the cotangent of dU/dt) back to
+//                the K stencil cells through LDS accumulators, and each cell
+//                applies its flux Jacobian once and writes out.
+//  k_faces_vjp_scalar, k_gather_vjp   scalar system: one thread per face
+//                writes the K stencil contributions per face and slot; one
+//                thread per cell sums those of the faces whose stencils hold
+//                it, in a fixed order (no atomics).
 #pragma once
 
 #include "teno_kernels.h"
@@ -30,26 +32,28 @@ namespace tenom {
 // reverse of the branch-free helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void minmod2_vjp(double x, double y, double obar, double& xbar, double& ybar) {
-  const double lo = fmin(x, y), hi = fmax(x, y);
-  if (lo > 0.0) {
-    if (x <= y) xbar += obar; else ybar += obar;
-  } else if (hi < 0.0) {
-    if (x >= y) xbar += obar; else ybar += obar;
-  }
+  // branch-free: the derivative goes to the smaller magnitude (x on a tie)
+  // when both share a strict sign, nowhere otherwise
+  const bool pos = fmin(x, y) > 0.0, neg = fmax(x, y) < 0.0;
+  const bool px = pos ? (x <= y) : (x >= y);
+  const double g = (pos || neg) ? obar : 0.0;
+  xbar += px ? g : 0.0;
+  ybar += px ? 0.0 : g;
 }
 
 __device__ __forceinline__ void minmod4_vjp(const double (&a)[4], double obar, double (&abar)[4]) {
-  const double lo = fmin(fmin(a[0], a[1]), fmin(a[2], a[3]));
-  const double hi = fmax(fmax(a[0], a[1]), fmax(a[2], a[3]));
-  if (lo > 0.0) {
-    const int i01 = a[0] <= a[1] ? 0 : 1, i23 = a[2] <= a[3] ? 2 : 3;
-    const int i = a[i01] <= a[i23] ? i01 : i23;
-    abar[i] += obar;
-  } else if (hi < 0.0) {
-    const int i01 = a[0] >= a[1] ? 0 : 1, i23 = a[2] >= a[3] ? 2 : 3;
-    const int i = a[i01] >= a[i23] ? i01 : i23;
-    abar[i] += obar;
-  }
+  // pairs (0,1), (2,3), then the two winners; the first index wins a tie
+  const bool pos = fmin(fmin(a[0], a[1]), fmin(a[2], a[3])) > 0.0;
+  const bool neg = fmax(fmax(a[0], a[1]), fmax(a[2], a[3])) < 0.0;
+  const bool p01 = pos ? (a[0] <= a[1]) : (a[0] >= a[1]);
+  const bool p23 = pos ? (a[2] <= a[3]) : (a[2] >= a[3]);
+  const double v01 = p01 ? a[0] : a[1], v23 = p23 ? a[2] : a[3];
+  const bool pl = pos ? (v01 <= v23) : (v01 >= v23);
+  const double g = (pos || neg) ? obar : 0.0;
+  abar[0] += (pl && p01) ? g : 0.0;
+  abar[1] += (pl && !p01) ? g : 0.0;
+  abar[2] += (!pl && p23) ? g : 0.0;
+  abar[3] += (!pl && !p23) ? g : 0.0;
 }
 
 // fmin(0, x) / fmax(0, x): the derivative reaches x only when x is chosen
@@ -67,21 +71,21 @@ __device__ __forceinline__ void mp_bounds_vjp(const double (&D)[K - 1], const Te
   {
     const double m1 = fmin(0.0, dp), A1 = fmin(m1, s.md);
     const double m2 = fmin(0.0, s.ul), A2 = fmin(m2, s.lc);
-    if (A1 >= A2) {
-      if (m1 <= s.md) dpbar += lobar * zmin_d(dp); else mdbar += lobar;
-    } else {
-      if (m2 <= s.lc) ulbar += lobar * zmin_d(s.ul); else lcbar += lobar;
-    }
+    const bool s1 = A1 >= A2, t1 = m1 <= s.md, t2 = m2 <= s.lc;
+    dpbar += (s1 && t1) ? lobar * zmin_d(dp) : 0.0;
+    mdbar += (s1 && !t1) ? lobar : 0.0;
+    ulbar += (!s1 && t2) ? lobar * zmin_d(s.ul) : 0.0;
+    lcbar += (!s1 && !t2) ? lobar : 0.0;
   }
   // hi = fmin(B1, B2), B1 = fmax(fmax(0, dp), md), B2 = fmax(fmax(0, ul), lc)
   {
     const double n1 = fmax(0.0, dp), B1 = fmax(n1, s.md);
     const double n2 = fmax(0.0, s.ul), B2 = fmax(n2, s.lc);
-    if (B1 <= B2) {
-      if (n1 >= s.md) dpbar += hibar * zmax_d(dp); else mdbar += hibar;
-    } else {
-      if (n2 >= s.lc) ulbar += hibar * zmax_d(s.ul); else lcbar += hibar;
-    }
+    const bool s1 = B1 <= B2, t1 = n1 >= s.md, t2 = n2 >= s.lc;
+    dpbar += (s1 && t1) ? hibar * zmax_d(dp) : 0.0;
+    mdbar += (s1 && !t1) ? hibar : 0.0;
+    ulbar += (!s1 && t2) ? hibar * zmax_d(s.ul) : 0.0;
+    lcbar += (!s1 && !t2) ? hibar : 0.0;
   }
   // ul = 1.25 dm, md = dp/2 - dR/2, lc = dm/2 + (beta/3) dL
   double dmbar = 1.25 * ulbar + 0.5 * lcbar;
@@ -145,18 +149,12 @@ __device__ __forceinline__ void teno_m_vjp_given(const double (&v)[K], const Ten
     double lobar = 0.0, hibar = 0.0;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
+      // lim = fmin(fmax(c, lo), hi) on a nonsmooth candidate
       const double w = T::d(k) * rbar;
-      cbar[k] = 0.0;
-      if (smooth[k]) {
-        cbar[k] = w;
-      } else {
-        // lim = fmin(fmax(c, lo), hi)
-        if (fmax(c[k], ms.lo) <= ms.hi) {
-          if (c[k] >= ms.lo) cbar[k] = w; else lobar += w;
-        } else {
-          hibar += w;
-        }
-      }
+      const bool in_hi = fmax(c[k], ms.lo) <= ms.hi, ge_lo = c[k] >= ms.lo;
+      cbar[k] = (smooth[k] || (in_hi && ge_lo)) ? w : 0.0;
+      lobar += (!smooth[k] && in_hi && !ge_lo) ? w : 0.0;
+      hibar += (!smooth[k] && !in_hi) ? w : 0.0;
     }
     mp_bounds_vjp<K, LIM>(D, tp, ms, lobar, hibar, Dbar);
   } else {
@@ -174,27 +172,18 @@ __device__ __forceinline__ void teno_m_vjp_given(const double (&v)[K], const Ten
       const double B = tvd5_b<K>(D);
       const double sbar = 0.5 * fbar;
       double Bbar = 0.0;
-      if (dm > 0.0) {
-        // up = fmax(0, u1), u1 = fmin(u0, B), u0 = fmin(2 dm, 2 dp)
-        const double u0 = fmin(2.0 * dm, 2.0 * dp), u1 = fmin(u0, B);
-        if (!(0.0 >= u1)) {
-          if (u0 <= B) {
-            if (2.0 * dm <= 2.0 * dp) dmbar += 2.0 * sbar; else dpbar += 2.0 * sbar;
-          } else {
-            Bbar += sbar;
-          }
-        }
-      } else if (dm < 0.0) {
-        // dn = fmin(0, w1), w1 = fmax(w0, B), w0 = fmax(2 dm, 2 dp)
-        const double w0 = fmax(2.0 * dm, 2.0 * dp), w1 = fmax(w0, B);
-        if (!(0.0 <= w1)) {
-          if (w0 >= B) {
-            if (2.0 * dm >= 2.0 * dp) dmbar += 2.0 * sbar; else dpbar += 2.0 * sbar;
-          } else {
-            Bbar += sbar;
-          }
-        }
-      }
+      // dm > 0: up = fmax(0, u1), u1 = fmin(u0, B), u0 = fmin(2 dm, 2 dp)
+      // dm < 0: dn = fmin(0, w1), w1 = fmax(w0, B), w0 = fmax(2 dm, 2 dp)
+      const bool pos = dm > 0.0, neg = dm < 0.0;
+      const double u0 = pos ? fmin(2.0 * dm, 2.0 * dp) : fmax(2.0 * dm, 2.0 * dp);
+      const double u1 = pos ? fmin(u0, B) : fmax(u0, B);
+      const bool live = pos ? !(0.0 >= u1) : (neg && !(0.0 <= u1));
+      const bool first = pos ? (u0 <= B) : (u0 >= B);
+      const bool pick_m = pos ? (2.0 * dm <= 2.0 * dp) : (2.0 * dm >= 2.0 * dp);
+      const double g = live ? sbar : 0.0;
+      dmbar += (first && pick_m) ? 2.0 * g : 0.0;
+      dpbar += (first && !pick_m) ? 2.0 * g : 0.0;
+      Bbar += first ? 0.0 : g;
       // B = (-2 D[C0-2] + 11 dm + 24 dp - 3 D[C0+1]) / 30
       const double b30 = Bbar * (1.0 / 30.0);
       Dbar[C0 - 2] += -2.0 * b30;
@@ -239,6 +228,103 @@ __device__ __forceinline__ void teno_m_vjp(const double (&v)[K], const TenoParam
 #pragma unroll
   for (int k = 0; k < K - 2; ++k) mask |= (smooth[k] ? 1u : 0u) << k;
   teno_m_vjp_given<K, LIM>(v, tp, mask, rbar, vbar);
+}
+
+// Adjoint of one TENO-M reconstruction from its decision code (teno_m with
+// FLAGS): with every decision known the map is linear, so nothing of the
+// forward is recomputed.  All limiters but Van Albada, whose slope function
+// is differentiated at its value (teno_m_vjp_given).
+template <int K, int LIM>
+__device__ __forceinline__ void teno_m_vjp_code(uint32_t code, const TenoParams& tp, double rbar,
+                                                double (&vbar)[K]) {
+  static_assert(LIM != LIM_VA, "Van Albada needs the values");
+  using T = TenoTables<K>;
+  constexpr int NK = K - 2;
+  constexpr int C0 = K / 2 - 1;
+  double cbar[NK], Dbar[K - 1];
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) Dbar[j] = 0.0;
+  vbar[C0] += rbar;
+  if constexpr (LIM == LIM_TENO) {
+    double den = 0.0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) den = ((code >> k) & 1u) ? den + T::d(k) : den;
+    const double w = rbar * rcp(den);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) cbar[k] = ((code >> k) & 1u) ? T::d(k) * w : 0.0;
+  } else if constexpr (LIM == LIM_MP || LIM == LIM_MP_MM) {
+    double lobar = 0.0, hibar = 0.0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const double w = T::d(k) * rbar;
+      const uint32_t sel = (code >> (8 + 2 * k)) & 3u;
+      cbar[k] = sel == 0u ? w : 0.0;
+      lobar += sel == 1u ? w : 0.0;
+      hibar += sel == 2u ? w : 0.0;
+    }
+    const uint32_t lo = (code >> 20) & 7u, hi = (code >> 23) & 7u;
+    const uint32_t pr = (code >> 26) & 7u, pl = (code >> 29) & 7u;
+    double dpbar = (lo == 1u ? lobar : 0.0) + (hi == 1u ? hibar : 0.0);
+    const double mdbar = (lo == 2u ? lobar : 0.0) + (hi == 2u ? hibar : 0.0);
+    const double ulbar = (lo == 3u ? lobar : 0.0) + (hi == 3u ? hibar : 0.0);
+    const double lcbar = (lo == 4u ? lobar : 0.0) + (hi == 4u ? hibar : 0.0);
+    // ul = 1.25 dm, md = dp/2 - dR/2, lc = dm/2 + (beta/3) dL
+    const double dmbar = 1.25 * ulbar + 0.5 * lcbar;
+    dpbar += 0.5 * mdbar;
+    const double dRbar = -0.5 * mdbar, dLbar = tp.mp_beta3 * lcbar;
+    double d_im1bar = 0.0, d_ibar = 0.0, d_ip1bar = 0.0;
+    if constexpr (LIM == LIM_MP) {
+      // aR = (4 d_i - d_ip1, 4 d_ip1 - d_i, d_i, d_ip1), aL likewise at i-1/2
+      const double r0 = pr == 1u ? dRbar : 0.0, r1 = pr == 2u ? dRbar : 0.0;
+      const double r2 = pr == 3u ? dRbar : 0.0, r3 = pr == 4u ? dRbar : 0.0;
+      const double l0 = pl == 1u ? dLbar : 0.0, l1 = pl == 2u ? dLbar : 0.0;
+      const double l2 = pl == 3u ? dLbar : 0.0, l3 = pl == 4u ? dLbar : 0.0;
+      d_ibar += 4.0 * r0 - r1 + r2;
+      d_ip1bar += -r0 + 4.0 * r1 + r3;
+      d_im1bar += 4.0 * l0 - l1 + l2;
+      d_ibar += -l0 + 4.0 * l1 + l3;
+    } else {
+      // dR = minmod(d_i, d_ip1), dL = minmod(d_im1, d_i)
+      d_ibar += pr == 1u ? dRbar : 0.0;
+      d_ip1bar += pr == 2u ? dRbar : 0.0;
+      d_im1bar += pl == 1u ? dLbar : 0.0;
+      d_ibar += pl == 2u ? dLbar : 0.0;
+    }
+    // d_im1 = D[C0-1] - D[C0-2], d_i = D[C0] - D[C0-1], d_ip1 = D[C0+1] - D[C0]
+    Dbar[C0 - 2] -= d_im1bar;
+    Dbar[C0 - 1] += d_im1bar - d_ibar + dmbar;
+    Dbar[C0] += d_ibar - d_ip1bar + dpbar;
+    Dbar[C0 + 1] += d_ip1bar;
+  } else {
+    double fbar = 0.0;  // cotangent of the TVD-type flux
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const bool sm = (code >> k) & 1u;
+      const double w = T::d(k) * rbar;
+      cbar[k] = sm ? w : 0.0;
+      fbar += sm ? 0.0 : w;
+    }
+    const uint32_t sel = (code >> 8) & 3u;
+    if constexpr (LIM == LIM_TVD_MINMOD) {
+      // ftvd = minmod(dm, dp) / 2
+      Dbar[C0 - 1] += sel == 1u ? 0.5 * fbar : 0.0;
+      Dbar[C0] += sel == 2u ? 0.5 * fbar : 0.0;
+    } else {
+      // ftvd = (2 dm | 2 dp | B) / 2, B = (-2 D[C0-2] + 11 dm + 24 dp - 3 D[C0+1]) / 30
+      const double g = 0.5 * fbar;
+      const double b30 = (sel == 3u ? g : 0.0) * (1.0 / 30.0);
+      Dbar[C0 - 2] += -2.0 * b30;
+      Dbar[C0 - 1] += (sel == 1u ? 2.0 * g : 0.0) + 11.0 * b30;
+      Dbar[C0] += (sel == 2u ? 2.0 * g : 0.0) + 24.0 * b30;
+      Dbar[C0 + 1] += -3.0 * b30;
+    }
+  }
+  T::candidates_vjp(cbar, Dbar);
+#pragma unroll
+  for (int j = 0; j < K - 1; ++j) {
+    vbar[j + 1] += Dbar[j];
+    vbar[j] -= Dbar[j];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -333,24 +419,15 @@ struct FaceBars {
   double ut[NF - 2], b1, b2, cinv, ct, Ht, q2;
 };
 
-template <int NF, int K>
-__device__ __forceinline__ void face_state(const double (&X)[K][NF], double gamma, FaceState<NF>& s) {
+// Roe average of the face between cells a (left) and b (right) and the
+// eigenvector constants, by the forward face's expressions.
+template <int NF>
+__device__ __forceinline__ void roe_state(const double (&Xa)[NF], const double (&Xb)[NF], double gamma,
+                                          FaceState<NF>& s) {
   constexpr int ND = NF - 2;
-  constexpr int H = K / 2;
   const double gm1 = gamma - 1.0;
-  s.alpha = 0.0;
-  s.mstar = 0;
-#pragma unroll
-  for (int m = 0; m < K; ++m) {
-    double Fm[NF], lam;
-    cell_physics<NF>(X[m], gamma, Fm, lam);
-    if (!(s.alpha >= lam)) {  // alpha = fmax(alpha, lam): the first maximum
-      s.alpha = lam;
-      s.mstar = m;
-    }
-  }
-  roe_input<NF>(X[H - 1], gamma, s.ra);
-  roe_input<NF>(X[H], gamma, s.rb);
+  roe_input<NF>(Xa, gamma, s.ra);
+  roe_input<NF>(Xb, gamma, s.rb);
   s.w = rcp(s.ra.rs + s.rb.rs);
 #pragma unroll
   for (int d = 0; d < ND; ++d) s.ut[d] = fma(s.ra.rs, s.ra.u[d], s.rb.rs * s.rb.u[d]) * s.w;
@@ -364,8 +441,8 @@ __device__ __forceinline__ void face_state(const double (&X)[K][NF], double gamm
   s.b2 = 0.5 * s.q2 * s.b1;
 }
 
-// Component Q of the left-eigenvector projection (the expressions of the
-// forward face, so the values are the same bits).
+// Row Q of the left-eigenvector projection (the expressions of the forward
+// face, so the values are the same bits).
 template <int NF, int Q>
 __device__ __forceinline__ double project_row(const FaceState<NF>& s, const double (&Y)[NF]) {
   constexpr int ND = NF - 2;
@@ -385,7 +462,35 @@ __device__ __forceinline__ double project_row(const FaceState<NF>& s, const doub
   }
 }
 
-// Adjoint of project_row: ob -> Yb and the shared cotangents.
+// Gradient of row Q of the projection with respect to the projected vector
+// (the row of L: constant across the face's stencil).
+template <int NF, int Q>
+__device__ __forceinline__ void project_row_grad(const FaceState<NF>& s, double (&g)[NF]) {
+  constexpr int ND = NF - 2;
+#pragma unroll
+  for (int r = 0; r < NF; ++r) g[r] = 0.0;
+  if constexpr (Q == 1) {
+    // w1 = Y0 - A, A = b2 Y0 + b1 (Y_E - ut . Y_mom)
+    g[0] = 1.0 - s.b2;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) g[1 + d] = s.b1 * s.ut[d];
+    g[NF - 1] = -s.b1;
+  } else if constexpr (Q == 0 || Q == NF - 1) {
+    // w = (A +- Bn cinv) / 2, Bn = ut0 Y0 - Y1
+    const double sg = (Q == 0) ? 1.0 : -1.0;
+    g[0] = 0.5 * fma(sg * s.ut[0], s.cinv, s.b2);
+    g[1] = 0.5 * fma(-s.b1, s.ut[0], -sg * s.cinv);
+#pragma unroll
+    for (int d = 1; d < ND; ++d) g[1 + d] = -0.5 * s.b1 * s.ut[d];
+    g[NF - 1] = 0.5 * s.b1;
+  } else {
+    // w = Y_Q - ut_{Q-1} Y0
+    g[0] = -s.ut[Q - 1];
+    g[Q] = 1.0;
+  }
+}
+
+// Adjoint of project_row: ob -> Yb and the cotangents of the constants.
 template <int NF, int Q>
 __device__ __forceinline__ void project_row_vjp(const FaceState<NF>& s, const double (&Y)[NF], double ob,
                                                 double (&Yb)[NF], FaceBars<NF>& b) {
@@ -426,60 +531,60 @@ __device__ __forceinline__ void project_row_vjp(const FaceState<NF>& s, const do
   }
 }
 
-// Per-field intermediates the forward pass keeps for the adjoint.
-template <int K>
-struct FieldKeep {
-  double vp[K], vm[K];  // doubled split values (vm mirrored)
-  double W[K], G[K];    // row Q of the projections of U and F
-  uint32_t mp, mm;      // smoothness decisions of the two reconstructions
-};
-
-// Field Q of the forward face: fc_Q = (TENO(g+) + TENO(g-)) / 2 (doubled split).
-template <int NF, int K, int LIM, bool ADAPT, int Q>
-__device__ __forceinline__ double field_forward(const double (&X)[K][NF], const FaceState<NF>& s, double gamma,
-                                                const TenoParams& tp, FieldKeep<K>& f) {
+// Left-eigenvector projection w = L Y of a conservative vector (the forward
+// face's expressions, so the values are the same bits).
+template <int NF>
+__device__ __forceinline__ void project_all(const FaceState<NF>& s, const double (&Y)[NF], double (&w)[NF]) {
+  constexpr int ND = NF - 2;
+  double um = 0.0;
 #pragma unroll
-  for (int m = 0; m < K; ++m) {
-    double Fm[NF], lam;
-    cell_physics<NF>(X[m], gamma, Fm, lam);
-    f.W[m] = project_row<NF, Q>(s, X[m]);
-    f.G[m] = project_row<NF, Q>(s, Fm);
-    lf_split2(f.G[m], s.alpha, f.W[m], f.vp[m], f.vm[K - 1 - m]);
-  }
-  f.mp = f.mm = 0u;
-  return 0.5 * (teno_m<K, LIM, true, ADAPT>(f.vp, tp, f.mp) + teno_m<K, LIM, true, ADAPT>(f.vm, tp, f.mm));
+  for (int d = 0; d < ND; ++d) um = fma(s.ut[d], Y[1 + d], um);
+  const double A = fma(s.b2, Y[0], s.b1 * (Y[NF - 1] - um));
+  const double Bn = fma(s.ut[0], Y[0], -Y[1]);
+  w[0] = 0.5 * fma(Bn, s.cinv, A);
+  w[1] = Y[0] - A;
+#pragma unroll
+  for (int t = 1; t < ND; ++t) w[1 + t] = fma(-s.ut[t], Y[0], Y[1 + t]);
+  w[NF - 1] = 0.5 * fma(-Bn, s.cinv, A);
 }
 
-// Adjoint of field Q: fcbar_Q -> Xbar (through the reconstructions, the
-// split, row Q of both projections, the cell fluxes and alpha) and the
-// shared cotangents.
-template <int NF, int K, int LIM, int Q>
-__device__ __forceinline__ void field_vjp(const double (&X)[K][NF], const FaceState<NF>& s, double gamma,
-                                          const TenoParams& tp, double fcbar, FieldKeep<K>& f,
-                                          double (&Xbar)[K][NF], FaceBars<NF>& b) {
-  double vpbar[K], vmbar[K];
+// Adjoint of project_all: wb -> Yb (added) and the cotangents of the
+// eigenvector constants (added to b).
+template <int NF>
+__device__ __forceinline__ void project_all_vjp(const FaceState<NF>& s, const double (&Y)[NF], const double (&wb)[NF],
+                                                double (&Yb)[NF], FaceBars<NF>& b) {
+  constexpr int ND = NF - 2;
+  double um = 0.0;
 #pragma unroll
-  for (int m = 0; m < K; ++m) vpbar[m] = vmbar[m] = 0.0;
-  teno_m_vjp_given<K, LIM>(f.vp, tp, f.mp, 0.5 * fcbar, vpbar);
-  teno_m_vjp_given<K, LIM>(f.vm, tp, f.mm, 0.5 * fcbar, vmbar);
-  double alphabar = 0.0;
+  for (int d = 0; d < ND; ++d) um = fma(s.ut[d], Y[1 + d], um);
+  const double Bn = fma(s.ut[0], Y[0], -Y[1]);
+  // w0 = (A + Bn cinv)/2, wE = (A - Bn cinv)/2, w1 = Y0 - A
+  const double Abar = 0.5 * (wb[0] + wb[NF - 1]) - wb[1];
+  const double hd = 0.5 * (wb[0] - wb[NF - 1]);
+  const double Bnbar = hd * s.cinv;
+  b.cinv += hd * Bn;
+  Yb[0] += wb[1];
+  // w_{1+t} = Y_{1+t} - ut_t Y0
 #pragma unroll
-  for (int m = 0; m < K; ++m) {
-    // vp[m] = G + alpha W, vm[K-1-m] = G - alpha W
-    const double pb = vpbar[m], mb = vmbar[K - 1 - m];
-    alphabar += f.W[m] * (pb - mb);
-    f.G[m] = pb + mb;
-    f.W[m] = s.alpha * (pb - mb);
+  for (int t = 1; t < ND; ++t) {
+    Yb[0] -= s.ut[t] * wb[1 + t];
+    Yb[1 + t] += wb[1 + t];
+    b.ut[t] -= Y[0] * wb[1 + t];
   }
+  // Bn = ut0 Y0 - Y1
+  b.ut[0] += Bnbar * Y[0];
+  Yb[0] += Bnbar * s.ut[0];
+  Yb[1] -= Bnbar;
+  // A = b2 Y0 + b1 (Y_E - um), um = ut . Y_mom
+  b.b2 += Abar * Y[0];
+  Yb[0] += Abar * s.b2;
+  b.b1 += Abar * (Y[NF - 1] - um);
+  Yb[NF - 1] += Abar * s.b1;
+  const double umbar = -Abar * s.b1;
 #pragma unroll
-  for (int m = 0; m < K; ++m) {
-    project_row_vjp<NF, Q>(s, X[m], f.W[m], Xbar[m], b);
-    double Fm[NF], lam, Fb[NF];
-    cell_physics<NF>(X[m], gamma, Fm, lam);
-#pragma unroll
-    for (int r = 0; r < NF; ++r) Fb[r] = 0.0;
-    project_row_vjp<NF, Q>(s, Fm, f.G[m], Fb, b);
-    cell_physics_vjp<NF>(X[m], gamma, Fb, m == s.mstar ? alphabar : 0.0, Xbar[m]);
+  for (int d = 0; d < ND; ++d) {
+    b.ut[d] += umbar * Y[1 + d];
+    Yb[1 + d] += umbar * s.ut[d];
   }
 }
 
@@ -517,12 +622,12 @@ __device__ __forceinline__ void backproj_vjp(const FaceState<NF>& s, const doubl
   }
 }
 
-// Shared cotangents -> Xbar: eigenvector constants, Roe average, Roe inputs.
-template <int NF, int K>
-__device__ __forceinline__ void shared_vjp(const double (&X)[K][NF], const FaceState<NF>& s, double gamma,
-                                           FaceBars<NF> b, double (&Xbar)[K][NF]) {
+// Shared cotangents -> Xbar of the two cells of the Roe average: through the
+// eigenvector constants, the Roe average and the Roe inputs.
+template <int NF>
+__device__ __forceinline__ void shared_vjp(const double (&Xa)[NF], const double (&Xb)[NF], const FaceState<NF>& s,
+                                           double gamma, FaceBars<NF> b, double (&Xabar)[NF], double (&Xbbar)[NF]) {
   constexpr int ND = NF - 2;
-  constexpr int H = K / 2;
   const double gm1 = gamma - 1.0;
   // b2 = q2 b1 / 2, b1 = (gamma-1) cinv^2, cinv = 1/ct, ct = sqrt((gamma-1)(Ht - q2/2))
   b.q2 += 0.5 * s.b1 * b.b2;
@@ -547,8 +652,8 @@ __device__ __forceinline__ void shared_vjp(const double (&X)[K][NF], const FaceS
   }
   rsabar += b.Ht * (s.ra.H - s.Ht) * s.w;
   rsbbar += b.Ht * (s.rb.H - s.Ht) * s.w;
-  roe_input_vjp<NF>(X[H - 1], gamma, rsabar, uabar, b.Ht * s.ra.rs * s.w, Xbar[H - 1]);
-  roe_input_vjp<NF>(X[H], gamma, rsbbar, ubbar, b.Ht * s.rb.rs * s.w, Xbar[H]);
+  roe_input_vjp<NF>(Xa, gamma, rsabar, uabar, b.Ht * s.ra.rs * s.w, Xabar);
+  roe_input_vjp<NF>(Xb, gamma, rsbbar, ubbar, b.Ht * s.rb.rs * s.w, Xbbar);
 }
 
 // Scalar advection f = a u: Fbar -> ubar.
@@ -646,101 +751,380 @@ __global__ __launch_bounds__(256) void k_faces_vjp_scalar(const double* __restri
   for (int m = 0; m < K; ++m) contrib[(long)m * ax.nfaces + t] = ub[m];
 }
 
-// Euler system: a workgroup of NF wavefronts handles 64 faces, wavefront q
-// (threadIdx.y, uniform in the wave) the characteristic field q.  Every wave
-// recomputes the shared face state; the forward field results are exchanged
-// through LDS for the back-projection; each wave pushes its cotangents back
-// to the stencil (the shared ones included: the map is linear in them) and
-// the NF partial stencil cotangents are summed in LDS in the order q = 0,
-// 1, ... .
+// Doubled split values of field Q at one face from the staged cells.
+template <int NF, int K, int Q, int P>
+__device__ __forceinline__ void field_split(const double* sX, const double* sF, int t, const FaceState<NF>& s,
+                                            double (&vp)[K], double (&vm)[K], double (&W)[K]) {
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    double X[NF], F[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      X[r] = sX[r * P + t + m];
+      F[r] = sF[r * P + t + m];
+    }
+    W[m] = project_row<NF, Q>(s, X);
+    lf_split2(project_row<NF, Q>(s, F), s.alpha, W[m], vp[m], vm[K - 1 - m]);
+  }
+}
+
+// Forward of field Q at one face: fc_Q = (TENO(g+) + TENO(g-)) / 2 (doubled
+// split), with the decision codes of both reconstructions and W_m = row Q
+// of L applied to the stencil states (kept for the reverse).
+template <int NF, int K, int LIM, bool ADAPT, int Q, int P>
+__device__ __forceinline__ double field_fwd(const double* sX, const double* sF, int t, const FaceState<NF>& s,
+                                            const TenoParams& tp, double (&W)[K], uint32_t& cp, uint32_t& cm) {
+  double vp[K], vm[K];
+  field_split<NF, K, Q, P>(sX, sF, t, s, vp, vm, W);
+  cp = cm = 0u;
+  return 0.5 * (teno_m<K, LIM, true, ADAPT>(vp, tp, cp) + teno_m<K, LIM, true, ADAPT>(vm, tp, cm));
+}
+
+// Ordering of LDS accesses between lanes of one wavefront: the hardware
+// executes a wavefront's LDS instructions in order, and this keeps the
+// compiler from moving accesses across the point.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wavefront accumulators of one field and half tile: slot lane + m of
+// each [NF][AP] array collects stencil cell m of the face of `lane`.
+struct FieldAcc {
+  double* x;    // cotangent of the cell state (direct part)
+  double* f;    // cotangent of the cell's physical flux
+  double* lam;  // cotangent of the cell's signal speed
+  int lane;
+  bool live;
+};
+
+// Reverse of field Q: fcbar -> the cotangents of the field's split values
+// (from the decision codes), then of the stencil states and fluxes through
+// row Q of L (added to the wave's accumulators), of alpha, and of the
+// eigenvector constants (b).
+template <int NF, int K, int LIM, int Q, int P, int AP>
+__device__ __forceinline__ void field_rev(const double* sX, const double* sF, int t, const FaceState<NF>& s,
+                                          const TenoParams& tp, const double (&W)[K], uint32_t cp, uint32_t cm,
+                                          double fcbar, const FieldAcc& a, FaceBars<NF>& b) {
+  double vpbar[K], vmbar[K];
+#pragma unroll
+  for (int m = 0; m < K; ++m) vpbar[m] = vmbar[m] = 0.0;
+  if constexpr (LIM == LIM_VA) {
+    double vp[K], vm[K], Wd[K];
+    field_split<NF, K, Q, P>(sX, sF, t, s, vp, vm, Wd);
+    teno_m_vjp_given<K, LIM>(vp, tp, cp, 0.5 * fcbar, vpbar);
+    teno_m_vjp_given<K, LIM>(vm, tp, cm, 0.5 * fcbar, vmbar);
+  } else {
+    teno_m_vjp_code<K, LIM>(cp, tp, 0.5 * fcbar, vpbar);
+    teno_m_vjp_code<K, LIM>(cm, tp, 0.5 * fcbar, vmbar);
+  }
+  double g[NF];
+  project_row_grad<NF, Q>(s, g);
+  constexpr bool full = (Q == 0 || Q == 1 || Q == NF - 1);
+  double alphabar = 0.0;
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    // vp[m] = G + alpha W, vm[K-1-m] = G - alpha W
+    const double pb = vpbar[m], mb = vmbar[K - 1 - m];
+    alphabar += W[m] * (pb - mb);
+    const double Wb = s.alpha * (pb - mb), Gb = pb + mb;
+    double X[NF], F[NF], dummy[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      X[r] = sX[r * P + t + m];
+      F[r] = sF[r * P + t + m];
+      dummy[r] = 0.0;
+    }
+    // the constants' cotangents (the stencil part is Wb g, Gb g)
+    project_row_vjp<NF, Q>(s, X, Wb, dummy, b);
+    project_row_vjp<NF, Q>(s, F, Gb, dummy, b);
+    wave_lds_order();
+    if (a.live) {
+#pragma unroll
+      for (int r = 0; r < NF; ++r) {
+        if (full || r == 0 || r == Q) {
+          a.x[r * AP + a.lane + m] += Wb * g[r];
+          a.f[r * AP + a.lane + m] += Gb * g[r];
+        }
+      }
+    }
+  }
+  // alphabar to slot lane + mstar, one step per m (lanes would meet otherwise)
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    wave_lds_order();
+    if (a.live && m == s.mstar) a.lam[a.lane + m] += alphabar;
+  }
+}
+
+// Tiled Euler adjoint along one axis, one characteristic field per
+// wavefront.  A workgroup of (FW faces) x (NF fields) threads owns the cells
+// [c0, c1) of one line (c1 - c0 <= FW + 1 - K).
+//  1. stage the positions its faces read: state, physical flux, signal
+//     speed, and the cotangent of dU/dt (0 beyond a transmissive end);
+//  2. thread (f, q) recomputes field q of face f with the decision codes of
+//     its two reconstructions; the field values go to LDS;
+//  3. each thread back-projects the face cotangent, reverses its field from
+//     the codes and adds the stencil contributions (row q of L transposed)
+//     to accumulators of its own wavefront (field q, half tile h; in step m
+//     lane l adds to slot l + m, so the lanes of a step meet nowhere); the
+//     fields' cotangents of the eigenvector constants are summed in LDS, one
+//     field after the other;
+//  4. one wavefront per half tile reverses the Roe average once per face;
+//  5. each owned cell sums its slots over fields and half tiles (and, at an
+//     end of a transmissive line, the clamped positions beyond it), applies
+//     its flux Jacobian and signal-speed derivative once and writes out.
+// The order of every sum is fixed.  Blocks on one XCD (blockIdx mod 8) take
+// consecutive lines, so the lines of a strided axis that share cache lines
+// meet in one L2.
+struct VjpTiles {
+  long nlines;  // lines along the axis
+  int own;      // cells per tile (FW - K + 1)
+};
+
+template <int NF, int K>
+struct VjpTileShape {
+  static constexpr int FW = 128;              // faces per tile
+  static constexpr int P = FW + 2 * (K - 1);  // positions staged by a full tile
+  static constexpr int AP = 64 + K - 1;       // accumulator slots per half tile
+  static constexpr int NB = NF + 4;           // cotangents of the eigenvector constants
+};
+
+template <int NF>
+__device__ __forceinline__ void bars_to_array(const FaceBars<NF>& b, double* o) {
+#pragma unroll
+  for (int d = 0; d < NF - 2; ++d) o[d] = b.ut[d];
+  o[NF - 2] = b.b1;
+  o[NF - 1] = b.b2;
+  o[NF] = b.cinv;
+  o[NF + 1] = b.ct;
+  o[NF + 2] = b.Ht;
+  o[NF + 3] = b.q2;
+}
+
+template <int NF>
+__device__ __forceinline__ void array_to_bars(const double* o, FaceBars<NF>& b) {
+#pragma unroll
+  for (int d = 0; d < NF - 2; ++d) b.ut[d] = o[d];
+  b.b1 = o[NF - 2];
+  b.b2 = o[NF - 1];
+  b.cinv = o[NF];
+  b.ct = o[NF + 1];
+  b.Ht = o[NF + 2];
+  b.q2 = o[NF + 3];
+}
+
 template <int NF, int K, int LIM, bool ADAPT>
-__global__ __launch_bounds__(64 * NF) void k_faces_vjp_euler(const double* __restrict__ U,
-                                                             const double* __restrict__ Lbar,
-                                                             double* __restrict__ contrib, VjpAxis ax, int fld0,
-                                                             int fld1, int fld2, int fld3, int fld4, FaceParams fp) {
-  __shared__ double fcs[NF][64];
-  __shared__ double acc[K * NF][64];
-  const int lane = threadIdx.x;
-  const int q = threadIdx.y;
-  const long t = (long)blockIdx.x * 64 + lane;
-  const bool valid = t < ax.nfaces;
-  const long tt = valid ? t : ax.nfaces - 1;  // every thread takes part in the barriers
+__global__ __launch_bounds__(128 * NF) void k_vjp_tile(const double* __restrict__ U,
+                                                       const double* __restrict__ Lbar, double* __restrict__ out,
+                                                       VjpAxis ax, VjpTiles tl, int fld0, int fld1, int fld2,
+                                                       int fld3, int fld4, FaceParams fp, double scale, int acc) {
+  using S = VjpTileShape<NF, K>;
+  constexpr int FW = S::FW, P = S::P, AP = S::AP, NB = S::NB, H = K / 2;
+  __shared__ double sX[NF * P], sF[NF * P], sLam[P], sLb[NF * P], fcs[NF * FW], bS[NB * FW];
+  __shared__ double aX[NF * 2][NF * AP], aF[NF * 2][NF * AP], aL[NF * 2][AP];
+  long g = blockIdx.x;
+  const long B = gridDim.x;
+  if ((B & 7) == 0) g = (g & 7) * (B >> 3) + (g >> 3);
+  const long line = g % tl.nlines;
+  const int tile = (int)(g / tl.nlines);
   Line L;
-  int j;
-  vjp_face_line(ax, tt, L, j);
-  const long N = (long)ax.nx * ax.ny * ax.nz;
+  if (ax.axis == 0) {
+    L = Line{line * ax.nx, 1, ax.n, ax.bc};
+  } else if (ax.axis == 1) {
+    const long x = line % ax.nx, z = line / ax.nx;
+    L = Line{x + (long)ax.nx * ax.ny * z, ax.nx, ax.n, ax.bc};
+  } else {
+    L = Line{line, (long)ax.nx * ax.ny, ax.n, ax.bc};
+  }
   const int fall[5] = {fld0, fld1, fld2, fld3, fld4};
   int fld[NF];
 #pragma unroll
-  for (int r = 0; r < NF; ++r) fld[r] = fall[r];
-  double X[K][NF], Xbar[K][NF];
+  for (int q = 0; q < NF; ++q) fld[q] = fall[q];
+  const long N = (long)ax.nx * ax.ny * ax.nz;
+  const bool per = (ax.bc == 0);
+  const int n = ax.n;
+  const int c0 = tile * tl.own;
+  const int ncell = min(n, c0 + tl.own) - c0;
+  const int nface = ncell + K - 1;
+  const int npos = nface + K - 1;
+  const int pp0 = c0 - K + 1;  // position of slot 0
+  const int f = threadIdx.x, q = threadIdx.y;
+  const int tid = q * FW + f;
+  const int half = f >> 6, lane = f & 63;
+
+  // 1. staging; accumulators and the constants' cotangents cleared
+  for (int i = tid; i < npos; i += FW * NF) {
+    const int pos = pp0 + i;
+    const long cell = cell_at(L, pos);
+    const bool inside = per || (pos >= 0 && pos < n);
+    double X[NF], F[NF], lam;
 #pragma unroll
-  for (int m = 0; m < K; ++m) {
-    const long cell = cell_at(L, j - K / 2 + m);
+    for (int r = 0; r < NF; ++r) X[r] = U[fld[r] * N + cell];
+    cell_physics<NF>(X, fp.gamma, F, lam);
 #pragma unroll
     for (int r = 0; r < NF; ++r) {
-      X[m][r] = U[(long)fld[r] * N + cell];
-      Xbar[m][r] = 0.0;
+      sX[r * P + i] = X[r];
+      sF[r * P + i] = F[r];
+      sLb[r * P + i] = inside ? Lbar[fld[r] * N + cell] : 0.0;
     }
+    sLam[i] = lam;
   }
-  FaceState<NF> s;
-  face_state<NF, K>(X, fp.gamma, s);
-  // forward field q (its intermediates kept for the adjoint)
-  FieldKeep<K> keep;
-  double fcq = 0.0;
-  switch (q) {
-    case 0: fcq = field_forward<NF, K, LIM, ADAPT, 0>(X, s, fp.gamma, fp.tp, keep); break;
-    case 1: fcq = field_forward<NF, K, LIM, ADAPT, 1>(X, s, fp.gamma, fp.tp, keep); break;
-    case 2: fcq = field_forward<NF, K, LIM, ADAPT, 2>(X, s, fp.gamma, fp.tp, keep); break;
-    default:
-      if constexpr (NF > 3) {
-        if (q == 3) fcq = field_forward<NF, K, LIM, ADAPT, 3>(X, s, fp.gamma, fp.tp, keep);
-      }
-      if constexpr (NF > 4) {
-        if (q == 4) fcq = field_forward<NF, K, LIM, ADAPT, 4>(X, s, fp.gamma, fp.tp, keep);
-      }
-      break;
-  }
-  fcs[q][lane] = fcq;
-  __syncthreads();
-  double fc[NF], Fhbar[NF], fcbar[NF];
+  for (int i = tid; i < NF * 2 * AP; i += FW * NF) {
+    const int w = i / AP, e = i - w * AP;
 #pragma unroll
-  for (int r = 0; r < NF; ++r) fc[r] = fcs[r][lane];
-  face_cotangent<NF>(ax, L, j, N, fld, Lbar, Fhbar);
+    for (int r = 0; r < NF; ++r) aX[w][r * AP + e] = aF[w][r * AP + e] = 0.0;
+    aL[w][e] = 0.0;
+  }
+  for (int i = tid; i < NB * FW; i += FW * NF) bS[i] = 0.0;
+  __syncthreads();
+
+  // 2. forward of field q at face f, with its decision codes
+  const int j = c0 - H + 1 + f;  // face of this thread: between positions j-1 and j
+  const bool live = f < nface && (per || (j >= 0 && j <= n));
+  const bool wave_live = __ballot(live) != 0;
+  const int t = f < nface ? f : nface - 1;  // staged slots for every lane
+  FaceState<NF> s;
+  double W[K];
+  uint32_t cp = 0u, cm = 0u;
+  if (wave_live) {
+    s.alpha = 0.0;
+    s.mstar = 0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const double lam = sLam[t + m];
+      if (!(s.alpha >= lam)) {  // alpha = fmax(alpha, lam): the first maximum
+        s.alpha = lam;
+        s.mstar = m;
+      }
+    }
+    double Xa[NF], Xb[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      Xa[r] = sX[r * P + t + H - 1];
+      Xb[r] = sX[r * P + t + H];
+    }
+    roe_state<NF>(Xa, Xb, fp.gamma, s);
+    double fc = 0.0;
+    switch (q) {
+      case 0: fc = field_fwd<NF, K, LIM, ADAPT, 0, P>(sX, sF, t, s, fp.tp, W, cp, cm); break;
+      case 1: fc = field_fwd<NF, K, LIM, ADAPT, 1, P>(sX, sF, t, s, fp.tp, W, cp, cm); break;
+      case 2:
+        if constexpr (NF > 2) fc = field_fwd<NF, K, LIM, ADAPT, 2, P>(sX, sF, t, s, fp.tp, W, cp, cm);
+        break;
+      case 3:
+        if constexpr (NF > 3) fc = field_fwd<NF, K, LIM, ADAPT, 3, P>(sX, sF, t, s, fp.tp, W, cp, cm);
+        break;
+      default:
+        if constexpr (NF > 4) fc = field_fwd<NF, K, LIM, ADAPT, 4, P>(sX, sF, t, s, fp.tp, W, cp, cm);
+        break;
+    }
+    fcs[q * FW + f] = fc;
+  }
+  __syncthreads();
+
+  // 3. back-projection and the reverse of field q
   FaceBars<NF> b;
 #pragma unroll
   for (int d = 0; d < NF - 2; ++d) b.ut[d] = 0.0;
   b.b1 = b.b2 = b.cinv = b.ct = b.Ht = b.q2 = 0.0;
-  backproj_vjp<NF>(s, fc, Fhbar, fcbar, b, q == 0);
-  switch (q) {
-    case 0: field_vjp<NF, K, LIM, 0>(X, s, fp.gamma, fp.tp, fcbar[0], keep, Xbar, b); break;
-    case 1: field_vjp<NF, K, LIM, 1>(X, s, fp.gamma, fp.tp, fcbar[1], keep, Xbar, b); break;
-    case 2: field_vjp<NF, K, LIM, 2>(X, s, fp.gamma, fp.tp, fcbar[2], keep, Xbar, b); break;
-    default:
-      if constexpr (NF > 3) {
-        if (q == 3) field_vjp<NF, K, LIM, 3>(X, s, fp.gamma, fp.tp, fcbar[3], keep, Xbar, b);
-      }
-      if constexpr (NF > 4) {
-        if (q == 4) field_vjp<NF, K, LIM, 4>(X, s, fp.gamma, fp.tp, fcbar[4], keep, Xbar, b);
-      }
-      break;
+  if (wave_live) {
+    double fcv[NF], Fhbar[NF], fcbar[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      fcv[r] = fcs[r * FW + f];
+      Fhbar[r] = (sLb[r * P + t + H] - sLb[r * P + t + H - 1]) * ax.inv_dx;
+    }
+    backproj_vjp<NF>(s, fcv, Fhbar, fcbar, b, q == 0);
+    const FieldAcc a{aX[q * 2 + half], aF[q * 2 + half], aL[q * 2 + half], lane, live};
+    switch (q) {
+      case 0: field_rev<NF, K, LIM, 0, P, AP>(sX, sF, t, s, fp.tp, W, cp, cm, fcbar[0], a, b); break;
+      case 1: field_rev<NF, K, LIM, 1, P, AP>(sX, sF, t, s, fp.tp, W, cp, cm, fcbar[1], a, b); break;
+      case 2:
+        if constexpr (NF > 2) field_rev<NF, K, LIM, 2, P, AP>(sX, sF, t, s, fp.tp, W, cp, cm, fcbar[2], a, b);
+        break;
+      case 3:
+        if constexpr (NF > 3) field_rev<NF, K, LIM, 3, P, AP>(sX, sF, t, s, fp.tp, W, cp, cm, fcbar[3], a, b);
+        break;
+      default:
+        if constexpr (NF > 4) field_rev<NF, K, LIM, 4, P, AP>(sX, sF, t, s, fp.tp, W, cp, cm, fcbar[4], a, b);
+        break;
+    }
   }
-  shared_vjp<NF, K>(X, s, fp.gamma, b, Xbar);
-  // sum the partial stencil cotangents over the fields, q = 0, 1, ...
+  // the constants' cotangents summed over the fields, q = 0, 1, ...
 #pragma unroll 1
   for (int r = 0; r < NF; ++r) {
-    if (q == r) {
+    if (q == r && live) {
+      double o[NB];
+      bars_to_array<NF>(b, o);
 #pragma unroll
-      for (int m = 0; m < K; ++m)
-#pragma unroll
-        for (int c = 0; c < NF; ++c) acc[m * NF + c][lane] = (r == 0 ? 0.0 : acc[m * NF + c][lane]) + Xbar[m][c];
+      for (int k = 0; k < NB; ++k) bS[k * FW + f] += o[k];
     }
     __syncthreads();
   }
-  if (valid) {
-    for (int e = q; e < K * NF; e += NF) {
-      const int m = e / NF, c = e - m * NF;
-      contrib[((long)m * NF + fall[c]) * ax.nfaces + t] = acc[e][lane];
+
+  // 4. the Roe average, once per face (field 0's wavefronts)
+  if (q == 0 && wave_live) {
+    double o[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) o[k] = bS[k * FW + f];
+    FaceBars<NF> bt;
+    array_to_bars<NF>(o, bt);
+    double Xa[NF], Xb[NF], xa[NF], xb[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      Xa[r] = sX[r * P + t + H - 1];
+      Xb[r] = sX[r * P + t + H];
+      xa[r] = xb[r] = 0.0;
+    }
+    shared_vjp<NF>(Xa, Xb, s, fp.gamma, bt, xa, xb);
+    double* hx = aX[half];
+    wave_lds_order();
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < NF; ++r) hx[r * AP + lane + H - 1] += xa[r];
+    }
+    wave_lds_order();
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < NF; ++r) hx[r * AP + lane + H] += xb[r];
+    }
+  }
+  __syncthreads();
+
+  // 5. per owned cell: sum, flux Jacobian, write
+  if (tid < ncell) {
+    const int i = K - 1 + tid;  // slot of cell c0 + tid
+    const int c = c0 + tid;
+    const int lo = (!per && c == 0) ? i - H : i;
+    const int hi = (!per && c == n - 1) ? i + H : i;
+    double xs[NF], fs[NF], ls = 0.0, X[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      xs[r] = fs[r] = 0.0;
+      X[r] = sX[r * P + i];
+    }
+    for (int k = lo; k <= hi; ++k) {
+#pragma unroll
+      for (int w = 0; w < 2 * NF; ++w) {
+        const int e = k - 64 * (w & 1);  // slot k of half tile w & 1
+        if (e >= 0 && e < AP) {
+#pragma unroll
+          for (int r = 0; r < NF; ++r) {
+            xs[r] += aX[w][r * AP + e];
+            fs[r] += aF[w][r * AP + e];
+          }
+          ls += aL[w][e];
+        }
+      }
+    }
+    cell_physics_vjp<NF>(X, fp.gamma, fs, ls, xs);
+    const long cell = L.base + (long)c * L.stride;
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      const long o = (long)fld[r] * N + cell;
+      out[o] = (acc ? out[o] : 0.0) + scale * xs[r];
     }
   }
 }
@@ -825,16 +1209,23 @@ hipError_t launch_vjp(const VjpLaunch& a) {
     const unsigned fb = (unsigned)((a.ax.nfaces + 255) / 256);
     hipLaunchKernelGGL((k_faces_vjp_scalar<K, LIM, ADAPT>), dim3(fb), dim3(256), 0, a.stream, a.U, a.Lbar,
                        a.contrib, a.ax, a.fp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long N = (long)a.ax.nx * a.ax.ny * a.ax.nz;
+    const unsigned cb = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL((k_gather_vjp<NF, K>), dim3(cb), dim3(256), 0, a.stream, a.contrib, a.out, a.ax, a.scale,
+                       a.acc);
   } else {
-    const unsigned fb = (unsigned)((a.ax.nfaces + 63) / 64);
-    hipLaunchKernelGGL((k_faces_vjp_euler<NF, K, LIM, ADAPT>), dim3(fb), dim3(64, NF), 0, a.stream, a.U, a.Lbar,
-                       a.contrib, a.ax, a.fld[0], a.fld[1], a.fld[2], a.fld[3], a.fld[4], a.fp);
+    const long N = (long)a.ax.nx * a.ax.ny * a.ax.nz;
+    VjpTiles tl;
+    tl.nlines = N / a.ax.n;
+    tl.own = VjpTileShape<NF, K>::FW - K + 1;
+    const long ntile = (a.ax.n + tl.own - 1) / tl.own;
+    hipLaunchKernelGGL((k_vjp_tile<NF, K, LIM, ADAPT>), dim3((unsigned)(tl.nlines * ntile)),
+                       dim3(VjpTileShape<NF, K>::FW, NF), 0,
+                       a.stream, a.U, a.Lbar, a.out, a.ax, tl, a.fld[0], a.fld[1], a.fld[2], a.fld[3], a.fld[4],
+                       a.fp, a.scale, a.acc);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const long N = (long)a.ax.nx * a.ax.ny * a.ax.nz;
-  const unsigned cb = (unsigned)((N + 255) / 256);
-  hipLaunchKernelGGL((k_gather_vjp<NF, K>), dim3(cb), dim3(256), 0, a.stream, a.contrib, a.out, a.ax, a.scale, a.acc);
   return hipGetLastError();
 }
 

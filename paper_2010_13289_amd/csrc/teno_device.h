@@ -171,6 +171,47 @@ __device__ __forceinline__ void mp_bounds(const double (&D)[K - 1], const TenoPa
   s.hi = fmin(fmax(fmax(0.0, dp), s.md), fmax(fmax(0.0, s.ul), s.lc));
 }
 
+// Decision code of the MP limiter (bits relative to `shift`): which argument
+// the lower and upper bounds pass their derivative to (0 none, 1 dp, 2 md,
+// 3 ul, 4 lc; 3 bits each) and which argument each minmod of the curvature
+// measures picks (0 none, else 1 + index; 3 bits each).  Ties go to the
+// first argument, a bound of 0 passes nothing.
+__device__ __forceinline__ uint32_t minmod_pick(const double* a, int na) {
+  const bool pos = na == 4 ? fmin(fmin(a[0], a[1]), fmin(a[2], a[3])) > 0.0 : fmin(a[0], a[1]) > 0.0;
+  const bool neg = na == 4 ? fmax(fmax(a[0], a[1]), fmax(a[2], a[3])) < 0.0 : fmax(a[0], a[1]) < 0.0;
+  const bool p01 = pos ? (a[0] <= a[1]) : (a[0] >= a[1]);
+  uint32_t i = p01 ? 0u : 1u;
+  if (na == 4) {
+    const bool p23 = pos ? (a[2] <= a[3]) : (a[2] >= a[3]);
+    const double v01 = p01 ? a[0] : a[1], v23 = p23 ? a[2] : a[3];
+    const bool pl = pos ? (v01 <= v23) : (v01 >= v23);
+    i = pl ? i : (p23 ? 2u : 3u);
+  }
+  return (pos || neg) ? i + 1u : 0u;
+}
+
+template <int K, int LIM>
+__device__ __forceinline__ uint32_t mp_code(const double (&D)[K - 1], const MpState& s) {
+  constexpr int C0 = K / 2 - 1;
+  const double dp = D[C0];
+  uint32_t lo, hi;
+  {
+    const double m1 = fmin(0.0, dp), A1 = fmin(m1, s.md);
+    const double m2 = fmin(0.0, s.ul), A2 = fmin(m2, s.lc);
+    lo = (A1 >= A2) ? ((m1 <= s.md) ? (!(0.0 <= dp) ? 1u : 0u) : 2u)
+                    : ((m2 <= s.lc) ? (!(0.0 <= s.ul) ? 3u : 0u) : 4u);
+  }
+  {
+    const double n1 = fmax(0.0, dp), B1 = fmax(n1, s.md);
+    const double n2 = fmax(0.0, s.ul), B2 = fmax(n2, s.lc);
+    hi = (B1 <= B2) ? ((n1 >= s.md) ? (!(0.0 >= dp) ? 1u : 0u) : 2u)
+                    : ((n2 >= s.lc) ? (!(0.0 >= s.ul) ? 3u : 0u) : 4u);
+  }
+  constexpr int NA = (LIM == LIM_MP) ? 4 : 2;
+  const uint32_t r = minmod_pick(s.aR, NA), l = minmod_pick(s.aL, NA);
+  return lo | (hi << 3) | (r << 6) | (l << 9);
+}
+
 // TVD5 flux on the five cells centred at i, relative to v_i (Eqs. high order
 // TVD, TVDhighorder2, TVDbeta multiplied through by delta^-: division-free,
 // equal wherever the slope ratios exist).
@@ -189,8 +230,13 @@ constexpr double kVaDenMin = 2.2250738585072014e-308;
 
 __device__ __forceinline__ double va_den(double dm, double dp) { return fmax(fma(dp, dp, dm * dm), kVaDenMin); }
 
-// One TENO-M reconstruction (Secs. 2.2-3.3).  `bits` receives delta_k
-// (1 = smooth) in bit k when FLAGS.
+// One TENO-M reconstruction (Secs. 2.2-3.3).  When FLAGS, `bits` receives
+// delta_k (1 = smooth) in bit k and, above bit 7, the limiter's decisions
+// (what the adjoint with frozen branches needs): MP limiters, per candidate
+// k the median's choice in bits 8 + 2k (0 the candidate, 1 the lower bound,
+// 2 the upper) and mp_code in bits 20..31; TVD minmod, the minmod's pick in
+// bits 8..9 (0 none, 1 d-, 2 d+); TVD5, bits 8..9 (0 none, 1 2d-, 2 2d+,
+// 3 the fifth-order slope).
 template <int K, int LIM, bool FLAGS, bool ADAPT>
 __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams& tp, uint32_t& bits) {
   using T = TenoTables<K>;
@@ -216,13 +262,35 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
     mp_bounds<K, LIM>(D, tp, ms);
     lo = ms.lo;
     hi = ms.hi;
+    if constexpr (FLAGS) {
+      bits |= mp_code<K, LIM>(D, ms) << 20;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const uint32_t sel = smooth[k] ? 0u : (!(fmax(c[k], lo) <= hi) ? 2u : (c[k] >= lo ? 0u : 1u));
+        bits |= sel << (8 + 2 * k);
+      }
+    }
   } else if constexpr (LIM == LIM_TVD_MINMOD) {
     ftvd = 0.5 * minmod2(dm, dp);
+    if constexpr (FLAGS) {
+      const double a[2] = {dm, dp};
+      bits |= minmod_pick(a, 2) << 8;
+    }
   } else if constexpr (LIM == LIM_TVD5) {
     const double B = tvd5_b<K>(D);
     const double up = fmax(0.0, fmin(fmin(2.0 * dm, 2.0 * dp), B));
     const double dn = fmin(0.0, fmax(fmax(2.0 * dm, 2.0 * dp), B));
     ftvd = 0.5 * (dm > 0.0 ? up : (dm < 0.0 ? dn : 0.0));
+    if constexpr (FLAGS) {
+      // the same choices as the fmin/fmax chains, first argument on a tie
+      const bool pos = dm > 0.0, neg = dm < 0.0;
+      const double u0 = pos ? fmin(2.0 * dm, 2.0 * dp) : fmax(2.0 * dm, 2.0 * dp);
+      const double u1 = pos ? fmin(u0, B) : fmax(u0, B);
+      const bool live = pos ? !(0.0 >= u1) : (neg && !(0.0 <= u1));
+      const bool first = pos ? (u0 <= B) : (u0 >= B);
+      const bool pick_m = pos ? (2.0 * dm <= 2.0 * dp) : (2.0 * dm >= 2.0 * dp);
+      bits |= (live ? (first ? (pick_m ? 1u : 2u) : 3u) : 0u) << 8;
+    }
   } else if constexpr (LIM == LIM_VA) {
     const double phi = 2.0 * dp * dm * rcp(va_den(dm, dp));
     const double kp = phi * (1.0 / 3.0);
