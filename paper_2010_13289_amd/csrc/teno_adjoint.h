@@ -822,6 +822,12 @@ __device__ __forceinline__ void field_rev(const double* sX, const double* sF, in
   double g[NF];
   project_row_grad<NF, Q>(s, g);
   constexpr bool full = (Q == 0 || Q == 1 || Q == NF - 1);
+  // The constants' cotangents are bilinear in (row cotangent, projected
+  // vector): accumulate sum_m Wb_m U_m and sum_m Gb_m F_m and take the
+  // row's adjoint once with cotangent 1.
+  double SX[NF], SF[NF];
+#pragma unroll
+  for (int r = 0; r < NF; ++r) SX[r] = SF[r] = 0.0;
   double alphabar = 0.0;
 #pragma unroll
   for (int m = 0; m < K; ++m) {
@@ -829,16 +835,11 @@ __device__ __forceinline__ void field_rev(const double* sX, const double* sF, in
     const double pb = vpbar[m], mb = vmbar[K - 1 - m];
     alphabar += W[m] * (pb - mb);
     const double Wb = s.alpha * (pb - mb), Gb = pb + mb;
-    double X[NF], F[NF], dummy[NF];
 #pragma unroll
     for (int r = 0; r < NF; ++r) {
-      X[r] = sX[r * P + t + m];
-      F[r] = sF[r * P + t + m];
-      dummy[r] = 0.0;
+      SX[r] = fma(Wb, sX[r * P + t + m], SX[r]);
+      SF[r] = fma(Gb, sF[r * P + t + m], SF[r]);
     }
-    // the constants' cotangents (the stencil part is Wb g, Gb g)
-    project_row_vjp<NF, Q>(s, X, Wb, dummy, b);
-    project_row_vjp<NF, Q>(s, F, Gb, dummy, b);
     wave_lds_order();
     if (a.live) {
 #pragma unroll
@@ -856,6 +857,9 @@ __device__ __forceinline__ void field_rev(const double* sX, const double* sF, in
     wave_lds_order();
     if (a.live && m == s.mstar) a.lam[a.lane + m] += alphabar;
   }
+  double dummy[NF];
+  project_row_vjp<NF, Q>(s, SX, 1.0, dummy, b);
+  project_row_vjp<NF, Q>(s, SF, 1.0, dummy, b);
 }
 
 // Tiled Euler adjoint along one axis, one characteristic field per
@@ -885,9 +889,10 @@ struct VjpTiles {
 
 template <int NF, int K>
 struct VjpTileShape {
-  static constexpr int FW = 128;              // faces per tile
+  static constexpr int FW = 64;               // faces per tile (one wavefront per field)
   static constexpr int P = FW + 2 * (K - 1);  // positions staged by a full tile
-  static constexpr int AP = 64 + K - 1;       // accumulator slots per half tile
+  static constexpr int AP = 64 + K - 1;       // accumulator slots per wavefront
+  static constexpr int NH = FW / 64;          // wavefronts per field
   static constexpr int NB = NF + 4;           // cotangents of the eigenvector constants
 };
 
@@ -915,15 +920,24 @@ __device__ __forceinline__ void array_to_bars(const double* o, FaceBars<NF>& b) 
   b.q2 = o[NF + 3];
 }
 
+// Occupancy the tile kernel is compiled for: 3 wavefronts per SIMD (at most
+// 168 VGPRs; three 4-wavefront blocks of 46 KB LDS per CU), measured 20%
+// faster than 2 without spills; the 5-field tile (65 KB LDS, two blocks per
+// CU) cannot reach 3 and keeps 256 VGPRs.
+template <int NF>
+struct VjpOccupancy {
+  static constexpr int WAVES = NF >= 5 ? 2 : 3;
+};
+
 template <int NF, int K, int LIM, bool ADAPT>
-__global__ __launch_bounds__(128 * NF) void k_vjp_tile(const double* __restrict__ U,
+__global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccupancy<NF>::WAVES))) void k_vjp_tile(const double* __restrict__ U,
                                                        const double* __restrict__ Lbar, double* __restrict__ out,
                                                        VjpAxis ax, VjpTiles tl, int fld0, int fld1, int fld2,
                                                        int fld3, int fld4, FaceParams fp, double scale, int acc) {
   using S = VjpTileShape<NF, K>;
-  constexpr int FW = S::FW, P = S::P, AP = S::AP, NB = S::NB, H = K / 2;
-  __shared__ double sX[NF * P], sF[NF * P], sLam[P], sLb[NF * P], fcs[NF * FW], bS[NB * FW];
-  __shared__ double aX[NF * 2][NF * AP], aF[NF * 2][NF * AP], aL[NF * 2][AP];
+  constexpr int FW = S::FW, P = S::P, AP = S::AP, NB = S::NB, NH = S::NH, H = K / 2;
+  __shared__ double sX[NF * P], sF[NF * P], sLam[P], sLb[NF * P], fcs[NF * FW], bS[NF * NB * FW];
+  __shared__ double aX[NF * NH][NF * AP], aF[NF * NH][NF * AP], aL[NF * NH][AP];
   long g = blockIdx.x;
   const long B = gridDim.x;
   if ((B & 7) == 0) g = (g & 7) * (B >> 3) + (g >> 3);
@@ -971,13 +985,12 @@ __global__ __launch_bounds__(128 * NF) void k_vjp_tile(const double* __restrict_
     }
     sLam[i] = lam;
   }
-  for (int i = tid; i < NF * 2 * AP; i += FW * NF) {
+  for (int i = tid; i < NF * NH * AP; i += FW * NF) {
     const int w = i / AP, e = i - w * AP;
 #pragma unroll
     for (int r = 0; r < NF; ++r) aX[w][r * AP + e] = aF[w][r * AP + e] = 0.0;
     aL[w][e] = 0.0;
   }
-  for (int i = tid; i < NB * FW; i += FW * NF) bS[i] = 0.0;
   __syncthreads();
 
   // 2. forward of field q at face f, with its decision codes
@@ -1037,7 +1050,7 @@ __global__ __launch_bounds__(128 * NF) void k_vjp_tile(const double* __restrict_
       Fhbar[r] = (sLb[r * P + t + H] - sLb[r * P + t + H - 1]) * ax.inv_dx;
     }
     backproj_vjp<NF>(s, fcv, Fhbar, fcbar, b, q == 0);
-    const FieldAcc a{aX[q * 2 + half], aF[q * 2 + half], aL[q * 2 + half], lane, live};
+    const FieldAcc a{aX[q * NH + half], aF[q * NH + half], aL[q * NH + half], lane, live};
     switch (q) {
       case 0: field_rev<NF, K, LIM, 0, P, AP>(sX, sF, t, s, fp.tp, W, cp, cm, fcbar[0], a, b); break;
       case 1: field_rev<NF, K, LIM, 1, P, AP>(sX, sF, t, s, fp.tp, W, cp, cm, fcbar[1], a, b); break;
@@ -1052,23 +1065,24 @@ __global__ __launch_bounds__(128 * NF) void k_vjp_tile(const double* __restrict_
         break;
     }
   }
-  // the constants' cotangents summed over the fields, q = 0, 1, ...
-#pragma unroll 1
-  for (int r = 0; r < NF; ++r) {
-    if (q == r && live) {
-      double o[NB];
-      bars_to_array<NF>(b, o);
+  // each field's cotangents of the constants, summed in step 4
+  {
+    double o[NB];
+    bars_to_array<NF>(b, o);
 #pragma unroll
-      for (int k = 0; k < NB; ++k) bS[k * FW + f] += o[k];
-    }
-    __syncthreads();
+    for (int k = 0; k < NB; ++k) bS[(q * NB + k) * FW + f] = o[k];
   }
+  __syncthreads();
 
   // 4. the Roe average, once per face (field 0's wavefronts)
   if (q == 0 && wave_live) {
     double o[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) o[k] = bS[k * FW + f];
+    for (int k = 0; k < NB; ++k) {
+      o[k] = bS[k * FW + f];
+#pragma unroll
+      for (int r = 1; r < NF; ++r) o[k] += bS[(r * NB + k) * FW + f];
+    }
     FaceBars<NF> bt;
     array_to_bars<NF>(o, bt);
     double Xa[NF], Xb[NF], xa[NF], xb[NF];
@@ -1078,7 +1092,9 @@ __global__ __launch_bounds__(128 * NF) void k_vjp_tile(const double* __restrict_
       Xb[r] = sX[r * P + t + H];
       xa[r] = xb[r] = 0.0;
     }
-    shared_vjp<NF>(Xa, Xb, s, fp.gamma, bt, xa, xb);
+    FaceState<NF> sr;  // the Roe inputs again (cheaper than keeping them live)
+    roe_state<NF>(Xa, Xb, fp.gamma, sr);
+    shared_vjp<NF>(Xa, Xb, sr, fp.gamma, bt, xa, xb);
     double* hx = aX[half];
     wave_lds_order();
     if (live) {
@@ -1107,8 +1123,8 @@ __global__ __launch_bounds__(128 * NF) void k_vjp_tile(const double* __restrict_
     }
     for (int k = lo; k <= hi; ++k) {
 #pragma unroll
-      for (int w = 0; w < 2 * NF; ++w) {
-        const int e = k - 64 * (w & 1);  // slot k of half tile w & 1
+      for (int w = 0; w < NH * NF; ++w) {
+        const int e = k - 64 * (w % NH);  // slot k of wavefront w % NH of its field
         if (e >= 0 && e < AP) {
 #pragma unroll
           for (int r = 0; r < NF; ++r) {
