@@ -158,6 +158,16 @@ int tenom_flux_divergence(const tenom_grid* grid, int scheme, int limiter, doubl
 int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
                    double* U, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * tenom_rk3_step that also writes its stage states: U1 = U + dt L(U) and
+ * U2 = 3/4 U + 1/4 (U1 + dt L(U1)) into the caller's device arrays U1, U2
+ * (the state's shape, distinct from U and from each other), e.g. to hand
+ * them to tenom_rk3_step_vjp_stages.  Same workspace as tenom_rk3_step;
+ * the same kernels, so U is updated to the same bits.
+ */
+int tenom_rk3_step_stages(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                          double* U, double* U1, double* U2, void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace bytes tenom_rk3_step needs for this grid (0 if invalid). */
 size_t tenom_workspace_bytes(const tenom_grid* grid, int scheme);
 
@@ -221,6 +231,18 @@ size_t tenom_rk3_vjp_workspace_bytes(const tenom_grid* grid, int scheme);
  */
 int tenom_rk3_step_vjp(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
                        const double* U, double* Ubar, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * tenom_rk3_step_vjp with the step's stage states given (U1, U2 as written
+ * by tenom_rk3_step_stages from the same U, dt and scheme) instead of
+ * recomputed.  U, U1, U2 are not modified; Ubar must not alias any of them.
+ * Same workspace as tenom_rk3_step_vjp.  The stage states are not checked
+ * against U: the caller guarantees they are the ones the step from U made
+ * (otherwise the result is the adjoint of no step).
+ */
+int tenom_rk3_step_vjp_stages(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                              const double* U, const double* U1, const double* U2, double* Ubar, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* ---- batched independent 1D problems ------------------------------------ */
 /*

@@ -36,7 +36,7 @@ SYMBOLS = (
     "tenom_batch_set_tile", "tenom_batch_get_tile", "tenom_batch_rk3", "tenom_batch_rk3_graph",
     "tenom_batch_autotune", "tenom_batch_times", "tenom_batch_reset_times",
     "tenom_vjp_workspace_bytes", "tenom_flux_divergence_vjp", "tenom_rk3_vjp_workspace_bytes",
-    "tenom_rk3_step_vjp",
+    "tenom_rk3_step_vjp", "tenom_rk3_step_stages", "tenom_rk3_step_vjp_stages",
 )
 
 
@@ -145,6 +145,9 @@ def lib() -> C.CDLL:
         L.tenom_flux_divergence_vjp.argtypes = [gp, C.c_int, C.c_int, dp, dp, vp, vp, dp, vp, C.c_int, vp,
                                                 C.c_size_t, vp]
         L.tenom_rk3_step_vjp.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, vp, C.c_size_t, vp]
+        L.tenom_rk3_step_stages.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.tenom_rk3_step_vjp_stages.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, vp, vp, vp, C.c_size_t,
+                                                vp]
         _lib = L
     return _lib
 
@@ -232,14 +235,20 @@ class Workspace:
 
 
 def rk3_step(U, grid, scheme: int, limiter: int, C_T: float, gamma: float, dt: float,
-             workspace: Workspace | None = None, stream=None):
-    """One SSP-RK3 step in place on U; returns U."""
+             workspace: Workspace | None = None, stream=None, stages=None):
+    """One SSP-RK3 step in place on U; returns U.  stages = (U1, U2): device
+    arrays that receive the step's stage states (tenom_rk3_step_stages)."""
     g = Grid.of(grid)
     ptr = _state(U, g)
     ws = workspace if workspace is not None else Workspace(g, scheme, U.device)
     gc = g.to_c()
-    _check(lib().tenom_rk3_step(C.byref(gc), scheme, limiter, C_T, gamma, dt, ptr, ws.ptr, ws.nbytes,
-                                _stream(stream)))
+    if stages is None:
+        _check(lib().tenom_rk3_step(C.byref(gc), scheme, limiter, C_T, gamma, dt, ptr, ws.ptr, ws.nbytes,
+                                    _stream(stream)))
+    else:
+        p1, p2 = _state(stages[0], g, "U1"), _state(stages[1], g, "U2")
+        _check(lib().tenom_rk3_step_stages(C.byref(gc), scheme, limiter, C_T, gamma, dt, ptr, p1, p2, ws.ptr,
+                                           ws.nbytes, _stream(stream)))
     return U
 
 
@@ -417,14 +426,21 @@ def flux_divergence_vjp(U, Lbar, grid, scheme: int, limiter: int, C_T: float, ga
 
 
 def rk3_step_vjp(U, Ubar, grid, scheme: int, limiter: int, C_T: float, gamma: float, dt: float, workspace=None,
-                 stream=None):
-    """Ubar <- (d step(U) / d U)^T Ubar, in place; U is the step's input."""
+                 stream=None, stages=None):
+    """Ubar <- (d step(U) / d U)^T Ubar, in place; U is the step's input.
+    stages = (U1, U2): the step's stage states as rk3_step(stages=...) wrote
+    them (tenom_rk3_step_vjp_stages); otherwise they are recomputed."""
     g = Grid.of(grid)
     up, bp = _state(U, g), _state(Ubar, g, "Ubar")
     ws = workspace if workspace is not None else rk3_vjp_workspace(g, scheme, U.device)
     gc = g.to_c()
-    _check(lib().tenom_rk3_step_vjp(C.byref(gc), scheme, limiter, C_T, gamma, dt, up, bp, ws.ptr, ws.nbytes,
-                                    _stream(stream)))
+    if stages is None:
+        _check(lib().tenom_rk3_step_vjp(C.byref(gc), scheme, limiter, C_T, gamma, dt, up, bp, ws.ptr, ws.nbytes,
+                                        _stream(stream)))
+    else:
+        p1, p2 = _state(stages[0], g, "U1"), _state(stages[1], g, "U2")
+        _check(lib().tenom_rk3_step_vjp_stages(C.byref(gc), scheme, limiter, C_T, gamma, dt, up, p1, p2, bp,
+                                               ws.ptr, ws.nbytes, _stream(stream)))
     return Ubar
 
 
@@ -443,8 +459,9 @@ class Rk3Rollout:
 
     The forward keeps the state every `checkpoint` steps; the backward
     replays each segment from its checkpoint (the same kernels, so the same
-    decisions) and applies tenom_rk3_step_vjp in reverse order.  Memory:
-    steps/checkpoint + checkpoint states."""
+    decisions), keeping each step's input and stage states, and applies
+    tenom_rk3_step_vjp_stages in reverse order.  Memory: steps/checkpoint +
+    3 checkpoint states."""
 
     @staticmethod
     def apply(U0, grid, scheme, limiter, C_T, gamma, dt, steps, checkpoint=20):
@@ -469,13 +486,18 @@ class Rk3Rollout:
                 for k in range(nseg - 1, -1, -1):
                     first = k * checkpoint
                     last = min(steps, first + checkpoint)
-                    states = [ctx.saved[k].clone()]
-                    for _ in range(first, last - 1):
-                        V = states[-1].clone()
-                        rk3_step(V, g, scheme, limiter, C_T, gamma, dt, workspace=ws)
-                        states.append(V)
-                    for V in reversed(states):
-                        rk3_step_vjp(V, lam, g, scheme, limiter, C_T, gamma, dt, workspace=vws)
+                    # replay the segment, keeping every step's input and stage states
+                    steps_kept = []
+                    V = ctx.saved[k]
+                    for _ in range(first, last):
+                        W = V.clone()
+                        S1, S2 = torch.empty_like(V), torch.empty_like(V)
+                        rk3_step(W, g, scheme, limiter, C_T, gamma, dt, workspace=ws, stages=(S1, S2))
+                        steps_kept.append((V, S1, S2))
+                        V = W
+                    for V, S1, S2 in reversed(steps_kept):
+                        rk3_step_vjp(V, lam, g, scheme, limiter, C_T, gamma, dt, workspace=vws, stages=(S1, S2))
+                    del steps_kept
                 ctx.saved = None
                 return lam
 

@@ -430,22 +430,12 @@ size_t tenom_workspace_bytes(const tenom_grid* grid, int scheme) {
   return 3 * state;  // divergence accumulator R, stage states U1 and U2
 }
 
-int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt, double* U,
-                   void* ws, size_t ws_bytes, void* stream) {
-  g_err[0] = 0;
-  int rc = check_scheme(grid, scheme, limiter, C_T, gamma);
-  if (rc) return rc;
-  if (!U || !ws) return fail(TENOM_EINVAL, "U and ws must not be NULL");
-  if (!(dt > 0.0) || !isfinite(dt)) return fail(TENOM_EINVAL, "dt must be finite and > 0 (got %g)", dt);
-  if (((uintptr_t)ws & 255) != 0) return fail(TENOM_EINVAL, "workspace must be 256-byte aligned");
-  const size_t need = tenom_workspace_bytes(grid, scheme);
-  if (ws_bytes < need) return fail(TENOM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-  const size_t state = need / 3;
-  double* R = (double*)ws;
-  double* U1 = (double*)((char*)ws + state);
-  double* U2 = (double*)((char*)ws + 2 * state);
-  hipStream_t s = (hipStream_t)stream;
-  const int nd = grid->ndim;
+namespace {
+
+// The three stages of one SSP-RK3 step: U1, U2 written, U updated in place.
+int rk3_stages(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma, double dt, double* U, double* R,
+               double* U1, double* U2, hipStream_t s) {
+  const int nd = g->ndim;
   // (a, b) of U_out = a U^n + b (U_s + dt L(U_s)), stage inputs and outputs
   const double A[3] = {0.0, 0.75, 1.0 / 3.0};
   const double B[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -455,11 +445,47 @@ int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, 
     for (int ax = 0; ax < nd; ++ax) {
       const bool last = (ax == nd - 1);
       int mode = last ? (nd == 1 ? EPI_RK1 : EPI_RK) : (ax == 0 ? EPI_STORE : EPI_ACCUM);
-      rc = sweep(grid, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uo[st], A[st], B[st], dt, mode, s);
+      const int rc = sweep(g, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uo[st], A[st], B[st], dt, mode, s);
       if (rc) return rc;
     }
   }
   return TENOM_OK;
+}
+
+int rk3_step_checks(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                    const double* U, void* ws, size_t ws_bytes) {
+  int rc = check_scheme(grid, scheme, limiter, C_T, gamma);
+  if (rc) return rc;
+  if (!U || !ws) return fail(TENOM_EINVAL, "U and ws must not be NULL");
+  if (!(dt > 0.0) || !isfinite(dt)) return fail(TENOM_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+  if (((uintptr_t)ws & 255) != 0) return fail(TENOM_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = tenom_workspace_bytes(grid, scheme);
+  if (ws_bytes < need) return fail(TENOM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return TENOM_OK;
+}
+
+}  // namespace
+
+int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt, double* U,
+                   void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  const int rc = rk3_step_checks(grid, scheme, limiter, C_T, gamma, dt, U, ws, ws_bytes);
+  if (rc) return rc;
+  const size_t state = tenom_workspace_bytes(grid, scheme) / 3;
+  double* R = (double*)ws;
+  double* U1 = (double*)((char*)ws + state);
+  double* U2 = (double*)((char*)ws + 2 * state);
+  return rk3_stages(grid, scheme, limiter, C_T, gamma, dt, U, R, U1, U2, (hipStream_t)stream);
+}
+
+int tenom_rk3_step_stages(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                          double* U, double* U1, double* U2, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  const int rc = rk3_step_checks(grid, scheme, limiter, C_T, gamma, dt, U, ws, ws_bytes);
+  if (rc) return rc;
+  if (!U1 || !U2) return fail(TENOM_EINVAL, "U1 and U2 must not be NULL");
+  if (U1 == U || U2 == U || U1 == U2) return fail(TENOM_EINVAL, "U, U1 and U2 must be distinct arrays");
+  return rk3_stages(grid, scheme, limiter, C_T, gamma, dt, U, (double*)ws, U1, U2, (hipStream_t)stream);
 }
 
 int tenom_max_wave_speed(const tenom_grid* grid, double gamma, const double* U, double* out_host, void* stream) {
@@ -554,9 +580,10 @@ size_t tenom_rk3_vjp_workspace_bytes(const tenom_grid* grid, int scheme) {
   return 5 * state + contrib;  // R, U1, U2, Ubar1, Ubar2, face contributions
 }
 
-int tenom_rk3_step_vjp(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
-                       const double* U, double* Ubar, void* ws, size_t ws_bytes, void* stream) {
-  g_err[0] = 0;
+namespace {
+
+int rk3_vjp_checks(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                   const double* U, const double* Ubar, void* ws, size_t ws_bytes) {
   int rc = check_scheme(grid, scheme, limiter, C_T, gamma);
   if (rc) return rc;
   if (!U || !Ubar || !ws) return fail(TENOM_EINVAL, "U, Ubar and ws must not be NULL");
@@ -565,29 +592,15 @@ int tenom_rk3_step_vjp(const tenom_grid* grid, int scheme, int limiter, double C
   if (((uintptr_t)ws & 255) != 0) return fail(TENOM_EINVAL, "workspace must be 256-byte aligned");
   const size_t need = tenom_rk3_vjp_workspace_bytes(grid, scheme);
   if (ws_bytes < need) return fail(TENOM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-  const size_t state = align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
-  double* R = (double*)ws;
-  double* U1 = (double*)((char*)ws + state);
-  double* U2 = (double*)((char*)ws + 2 * state);
-  double* B1 = (double*)((char*)ws + 3 * state);
-  double* B2 = (double*)((char*)ws + 4 * state);
-  double* contrib = (double*)((char*)ws + 5 * state);
-  hipStream_t s = (hipStream_t)stream;
-  const int nd = grid->ndim;
+  return TENOM_OK;
+}
+
+// The reverse sweep of one step given its stage states.
+int rk3_vjp_core(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                 const double* U, const double* U1, const double* U2, double* Ubar, double* B1, double* B2,
+                 double* contrib, hipStream_t s) {
   const long M = (long)nfields(grid) * dims(grid).N;
-  // the stage states of the forward step, by the same sweeps as tenom_rk3_step
-  const double A[2] = {0.0, 0.75};
-  const double B[2] = {1.0, 0.25};
-  const double* Uin[2] = {U, U1};
-  double* Uo[2] = {U1, U2};
-  for (int st = 0; st < 2; ++st) {
-    for (int ax = 0; ax < nd; ++ax) {
-      const bool last = (ax == nd - 1);
-      int mode = last ? (nd == 1 ? EPI_RK1 : EPI_RK) : (ax == 0 ? EPI_STORE : EPI_ACCUM);
-      rc = sweep(grid, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uo[st], A[st], B[st], dt, mode, s);
-      if (rc) return rc;
-    }
-  }
+  int rc;
   // U3 = U/3 + 2/3 (U2 + dt L(U2)):  Ubar2 = 2/3 Ubar3 + 2/3 dt J(U2)^T Ubar3, Ubar_n = Ubar3 / 3
   if ((rc = axpby(B2, 2.0 / 3.0, Ubar, 0.0, nullptr, M, s))) return rc;
   if ((rc = vjp_axes(grid, scheme, limiter, C_T, gamma, U2, Ubar, 2.0 / 3.0 * dt, B2, true, contrib, s))) return rc;
@@ -599,6 +612,54 @@ int tenom_rk3_step_vjp(const tenom_grid* grid, int scheme, int limiter, double C
   // U1 = U + dt L(U):  Ubar_n += Ubar1 + dt J(U)^T Ubar1
   if ((rc = axpby(Ubar, 1.0, B1, 1.0, Ubar, M, s))) return rc;
   return vjp_axes(grid, scheme, limiter, C_T, gamma, U, B1, dt, Ubar, true, contrib, s);
+}
+
+}  // namespace
+
+int tenom_rk3_step_vjp(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                       const double* U, double* Ubar, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  const int rc = rk3_vjp_checks(grid, scheme, limiter, C_T, gamma, dt, U, Ubar, ws, ws_bytes);
+  if (rc) return rc;
+  const size_t state = align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
+  double* R = (double*)ws;
+  double* U1 = (double*)((char*)ws + state);
+  double* U2 = (double*)((char*)ws + 2 * state);
+  double* B1 = (double*)((char*)ws + 3 * state);
+  double* B2 = (double*)((char*)ws + 4 * state);
+  double* contrib = (double*)((char*)ws + 5 * state);
+  hipStream_t s = (hipStream_t)stream;
+  const int nd = grid->ndim;
+  // the stage states of the forward step, by the same sweeps as tenom_rk3_step
+  const double A[2] = {0.0, 0.75};
+  const double B[2] = {1.0, 0.25};
+  const double* Uin[2] = {U, U1};
+  double* Uo[2] = {U1, U2};
+  for (int st = 0; st < 2; ++st) {
+    for (int ax = 0; ax < nd; ++ax) {
+      const bool last = (ax == nd - 1);
+      int mode = last ? (nd == 1 ? EPI_RK1 : EPI_RK) : (ax == 0 ? EPI_STORE : EPI_ACCUM);
+      const int r = sweep(grid, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uo[st], A[st], B[st], dt, mode, s);
+      if (r) return r;
+    }
+  }
+  return rk3_vjp_core(grid, scheme, limiter, C_T, gamma, dt, U, U1, U2, Ubar, B1, B2, contrib, s);
+}
+
+int tenom_rk3_step_vjp_stages(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
+                              const double* U, const double* U1, const double* U2, double* Ubar, void* ws,
+                              size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  const int rc = rk3_vjp_checks(grid, scheme, limiter, C_T, gamma, dt, U, Ubar, ws, ws_bytes);
+  if (rc) return rc;
+  if (!U1 || !U2) return fail(TENOM_EINVAL, "U1 and U2 must not be NULL");
+  if ((const void*)U1 == (const void*)Ubar || (const void*)U2 == (const void*)Ubar)
+    return fail(TENOM_EINVAL, "Ubar must not alias U1 or U2");
+  const size_t state = align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
+  double* B1 = (double*)((char*)ws + 3 * state);
+  double* B2 = (double*)((char*)ws + 4 * state);
+  double* contrib = (double*)((char*)ws + 5 * state);
+  return rk3_vjp_core(grid, scheme, limiter, C_T, gamma, dt, U, U1, U2, Ubar, B1, B2, contrib, (hipStream_t)stream);
 }
 
 int tenom_profile_enable(int on) {

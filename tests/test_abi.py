@@ -92,6 +92,27 @@ def test_rk3_workspace_and_dt_errors(lib):
     assert lib.tenom_workspace_bytes(C.byref(grid(ndim=0)), 6) == 0
 
 
+def test_stage_entry_errors(lib):
+    """tenom_rk3_step_stages / tenom_rk3_step_vjp_stages reject missing or
+    aliased stage arrays before touching memory."""
+    g = grid()
+    need = lib.tenom_workspace_bytes(C.byref(g), 6)
+    ws = C.c_void_p(0x10000)
+    U1, U2 = C.c_void_p(0x3000), C.c_void_p(0x4000)
+    step = lib.tenom_rk3_step_stages
+    assert step(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, None, U2, ws, need, None) == T.EINVAL
+    assert step(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, DUMMY, U2, ws, need, None) == T.EINVAL
+    assert step(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, U1, U1, ws, need, None) == T.EINVAL
+    assert step(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, U1, U2, ws, need - 1, None) == T.EWORKSPACE
+    vneed = lib.tenom_rk3_vjp_workspace_bytes(C.byref(g), 6)
+    vjp = lib.tenom_rk3_step_vjp_stages
+    Ub = C.c_void_p(0x5000)
+    assert vjp(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, None, U2, Ub, ws, vneed, None) == T.EINVAL
+    assert vjp(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, U1, U2, U1, ws, vneed, None) == T.EINVAL
+    assert vjp(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, U1, U2, DUMMY, ws, vneed, None) == T.EINVAL
+    assert vjp(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, U1, U2, Ub, ws, vneed - 1, None) == T.EWORKSPACE
+
+
 def test_scheme_and_limiter_ids(lib):
     g = grid()
     bad = C.c_void_p(0x2000)
