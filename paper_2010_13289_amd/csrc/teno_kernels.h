@@ -11,7 +11,8 @@
 //                  epilogue.  A periodic row of <= 256 cells is one segment,
 //                  so every face and every cell is computed exactly once.
 //  k_sweep_march   sweep along y or z (strided).  Each lane owns one x
-//                  column (coalesced 512-byte rows per wave) and marches
+//                  column (coalesced 512-byte rows per wave; the block's
+//                  wavefronts take consecutive (line, segment) units) and marches
 //                  along the axis over a segment of cells, keeping the face's
 //                  K cells in an LDS ring and carrying the previous face
 //                  flux in registers.  The next face's new cell and the
@@ -294,10 +295,13 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
   __shared__ double ring[K * NF * T];
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int n_other = (axis == 1) ? p.nz : p.ny;
-  const int o = blockIdx.y * LINES + threadIdx.y;
-  if (x >= p.nx || o >= n_other) return;  // no block-wide barrier follows
+  // unit u = (line o of the other axis, segment s), o fastest: a 2D grid
+  // (one other line) still fills every wavefront of the block
+  const long u = ((long)blockIdx.z * gridDim.y + blockIdx.y) * LINES + threadIdx.y;
+  if (x >= p.nx || u >= (long)n_other * p.nseg) return;  // no block-wide barrier follows
+  const int o = (int)(u % n_other);
+  const int s = (int)(u / n_other);
   const int tid = threadIdx.y * 64 + threadIdx.x;
-  const int s = blockIdx.z;
   const long N = (long)p.nx * p.ny * p.nz;
   Line L;
   if (axis == 1)
@@ -424,7 +428,9 @@ hipError_t launch_sweep(const SweepLaunch& a) {
     p.nseg = (p.n + p.seg - 1) / p.seg;
     const int n_other = (a.axis == 1) ? a.nz : a.ny;
     constexpr int LINES = MarchShape<NF, K>::LINES;
-    dim3 grid((a.nx + 63) / 64, (n_other + LINES - 1) / LINES, p.nseg);
+    const long ub = ((long)n_other * p.nseg + LINES - 1) / LINES;  // blocks of units per x group
+    const long gy = ub < 65535 ? ub : 65535;
+    dim3 grid((a.nx + 63) / 64, (unsigned)gy, (unsigned)((ub + gy - 1) / gy));
     hipLaunchKernelGGL((k_sweep_march<NF, K, LIM, ADAPT>), grid, dim3(64, LINES), 0, a.stream, p, a.axis);
   }
   return hipGetLastError();

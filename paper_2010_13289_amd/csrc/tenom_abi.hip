@@ -217,12 +217,14 @@ int march_segment(int n, int nx, int n_other) {
   }
   if (env > 0) return env;
   // aim for >= 4096 waves (two full rounds at two waves per SIMD on 256
-  // CUs) while keeping the one redundant face per segment below ~3%
+  // CUs); segments of at least 8 cells (one redundant face per segment:
+  // 8-cell segments measured faster than 4, 16 or 32 on a 1024^2 y sweep,
+  // whose x groups alone give only 16 waves)
   const long waves_per_set = (long)((nx + 63) / 64) * n_other;
   long nseg = (4096 + waves_per_set - 1) / waves_per_set;
   if (nseg < 1) nseg = 1;
   long seg = (n + nseg - 1) / nseg;
-  if (seg < 32) seg = (n < 32) ? n : 32;
+  if (seg < 8) seg = (n < 8) ? n : 8;
   return (int)seg;
 }
 
