@@ -76,10 +76,11 @@ BYTES_PER_CELL_STEP = 320
 # by 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB device copy reads
 # as).  They describe the kernels built from the sources whose digest is
 # TRAFFIC_SOURCE_DIGEST and are reported as null for any other build.
-TRAFFIC_SOURCE_DIGEST = "0a31da1c1d5f25a08d0b0087367db6c3d10953ecc5aa0a7ba656bbd4d2442563"
-MEASURED_TRAFFIC = {"sweep_x": 1.3425e9, "sweep_y": 2.0765e9, "sweep_z": 2.5239e9,
-                    # batched sweep, 4096 problems, averaged over the stages
-                    "batch_sweep": 1.2623e9}
+TRAFFIC_SOURCE_DIGEST = "e9cf336cc679e1cbc286173edcbb492e0ff560bde473a85c42fb77896073e1e6"
+MEASURED_TRAFFIC = {"sweep_x": 1.3425e9, "sweep_y": 2.0765e9, "sweep_z": 2.5240e9}
+# batched sweep, 4096 problems, averaged over the stages, per tile shape
+# (64x1, 128x1, 128x2, 256x1, 256x2, 512x1): smaller tiles re-read more halo
+MEASURED_TRAFFIC_BATCH = (1.2753e9, 1.1487e9, 1.0866e9, 1.0863e9, 1.0554e9, 1.0551e9)
 
 
 def kernel_source_digest() -> str:
@@ -347,7 +348,7 @@ def run_batched(args):
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": (MEASURED_TRAFFIC["batch_sweep"] if kernel_source_digest() == TRAFFIC_SOURCE_DIGEST
+            "traffic": (MEASURED_TRAFFIC_BATCH[best] if kernel_source_digest() == TRAFFIC_SOURCE_DIGEST
                         else None),
             "avg_launch_ms": avg_s * 1e3,
             "flops_per_launch": FLOPS_PER_FACE_VECTOR_1D_K8 * faces_per_stage,
