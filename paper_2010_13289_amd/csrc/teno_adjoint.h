@@ -828,12 +828,14 @@ __device__ __forceinline__ void field_rev(const double* sX, const double* sF, in
   double SX[NF], SF[NF];
 #pragma unroll
   for (int r = 0; r < NF; ++r) SX[r] = SF[r] = 0.0;
+  // vp[m] = G + alpha W, vm[K-1-m] = G - alpha W: the field's part of alphabar
+  // first, so that it joins the stencil step of the maximising cell
   double alphabar = 0.0;
 #pragma unroll
+  for (int m = 0; m < K; ++m) alphabar += W[m] * (vpbar[m] - vmbar[K - 1 - m]);
+#pragma unroll
   for (int m = 0; m < K; ++m) {
-    // vp[m] = G + alpha W, vm[K-1-m] = G - alpha W
     const double pb = vpbar[m], mb = vmbar[K - 1 - m];
-    alphabar += W[m] * (pb - mb);
     const double Wb = s.alpha * (pb - mb), Gb = pb + mb;
 #pragma unroll
     for (int r = 0; r < NF; ++r) {
@@ -849,13 +851,8 @@ __device__ __forceinline__ void field_rev(const double* sX, const double* sF, in
           a.f[r * AP + a.lane + m] += Gb * g[r];
         }
       }
+      if (m == s.mstar) a.lam[a.lane + m] += alphabar;
     }
-  }
-  // alphabar to slot lane + mstar, one step per m (lanes would meet otherwise)
-#pragma unroll
-  for (int m = 0; m < K; ++m) {
-    wave_lds_order();
-    if (a.live && m == s.mstar) a.lam[a.lane + m] += alphabar;
   }
   double dummy[NF];
   project_row_vjp<NF, Q>(s, SX, 1.0, dummy, b);
