@@ -1092,16 +1092,17 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
     FaceState<NF> sr;  // the Roe inputs again (cheaper than keeping them live)
     roe_state<NF>(Xa, Xb, fp.gamma, sr);
     shared_vjp<NF>(Xa, Xb, sr, fp.gamma, bt, xa, xb);
-    double* hx = aX[half];
+    // one step: the left cell's part to field 0's slots, the right cell's to
+    // field 1's (both summed in step 5), so no two lanes meet
+    double* hx0 = aX[half];
+    double* hx1 = aX[NH + half];
     wave_lds_order();
     if (live) {
 #pragma unroll
-      for (int r = 0; r < NF; ++r) hx[r * AP + lane + H - 1] += xa[r];
-    }
-    wave_lds_order();
-    if (live) {
-#pragma unroll
-      for (int r = 0; r < NF; ++r) hx[r * AP + lane + H] += xb[r];
+      for (int r = 0; r < NF; ++r) {
+        hx0[r * AP + lane + H - 1] += xa[r];
+        hx1[r * AP + lane + H] += xb[r];
+      }
     }
   }
   __syncthreads();
