@@ -965,6 +965,17 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   const int tid = q * FW + f;
   const int half = f >> 6, lane = f & 63;
 
+  // the owned cell's previous output (accumulate mode), loaded first so that
+  // the load's latency hides behind the kernel instead of ending it
+  double prev[NF];
+#pragma unroll
+  for (int r = 0; r < NF; ++r) prev[r] = 0.0;
+  if (acc && tid < ncell) {
+    const long cell = L.base + (long)(c0 + tid) * L.stride;
+#pragma unroll
+    for (int r = 0; r < NF; ++r) prev[r] = out[(long)fld[r] * N + cell];
+  }
+
   // 1. staging; accumulators and the constants' cotangents cleared
   for (int i = tid; i < npos; i += FW * NF) {
     const int pos = pp0 + i;
@@ -1136,10 +1147,7 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
     cell_physics_vjp<NF>(X, fp.gamma, fs, ls, xs);
     const long cell = L.base + (long)c * L.stride;
 #pragma unroll
-    for (int r = 0; r < NF; ++r) {
-      const long o = (long)fld[r] * N + cell;
-      out[o] = (acc ? out[o] : 0.0) + scale * xs[r];
-    }
+    for (int r = 0; r < NF; ++r) out[(long)fld[r] * N + cell] = prev[r] + scale * xs[r];
   }
 }
 
