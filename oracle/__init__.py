@@ -98,6 +98,7 @@ def lib():
         L.or_max_wave_speed.argtypes = [gp, C.c_double, dp]
         L.or_max_wave_speed.restype = C.c_double
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
         if C.sizeof(Trace) != L.or_trace_size():
             raise RuntimeError("oracle trace layout mismatch")
         if L.or_init() != 0:
@@ -317,3 +318,8 @@ def max_wave_speed(U, grid, gamma):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops from now on."""
+    lib().or_set_num_threads(int(n))

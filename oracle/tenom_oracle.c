@@ -1093,3 +1093,12 @@ int or_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads of the following parallel regions (n >= 1); timing only. */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
