@@ -67,6 +67,24 @@ __device__ __forceinline__ double rcp1(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// 1/b_k of the K - 2 indicator denominators b_k = beta_k + eps, in pairs
+// from one reciprocal of each pair's product (1/b_0 = b_1 / (b_0 b_1)): one
+// transcendental per two denominators.  Relative error a few units in the
+// last place, as for rcp1; like rcp1 it only reaches the output through the
+// cutoff comparison.  Every b_k >= 4e-40, so no product underflows; a product
+// stays below 2^1000 (its reciprocal normal) while b_k < 2^500, i.e. for
+// split fluxes below about 1e75 in magnitude.
+template <int N>
+__device__ __forceinline__ void rcp_pairs(const double (&b)[N], double (&inv)[N]) {
+  static_assert(N % 2 == 0, "pairs of denominators");
+#pragma unroll
+  for (int k = 0; k < N; k += 2) {
+    const double r = rcp1(b[k] * b[k + 1]);
+    inv[k] = b[k + 1] * r;
+    inv[k + 1] = b[k] * r;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pieces of one TENO-M reconstruction at x_{i+1/2} from v[0..K-1] =
 // f_{i-K/2+1..i+K/2} (Secs. 2.2-3.3), computed relative to v_i in the
@@ -110,11 +128,15 @@ __device__ __forceinline__ void teno_cutoff(const double (&D)[K - 1], const Teno
   T::betas(D, beta, betaK);
   const double tau = fabs(fma(fma(4.0, beta[0], beta[1] + beta[2]), -1.0 / 6.0, betaK));
   // gamma_k and the cutoff: chi_k = gamma_k / sum < C_T  <=>  gamma_k < C_T sum
+  double b[NK], binv[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) b[k] = beta[k] + kEps2x;
+  rcp_pairs<NK>(b, binv);
   double g[NK];
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    const double s = fma(tau, rcp1(beta[k] + kEps2x), 1.0);
+    const double s = fma(tau, binv[k], 1.0);
     const double s2 = s * s;
     const double s4 = s2 * s2;
     g[k] = s4 * s2;
@@ -375,23 +397,47 @@ __device__ __forceinline__ void lf_split2(double f, double alpha, double u, doub
 // region, a uniform state) give exactly equal split values, zero
 // differences and beta_k = 0, whatever the instantiation around them.
 template <int NF>
-__device__ __forceinline__ void cell_physics(const double (&X)[NF], double gamma, double (&F)[NF], double& lam) {
+struct CellPrim {
+  double rinv, un, e, p;  // 1/rho, normal velocity, internal energy per volume, pressure
+};
+
+template <int NF>
+__device__ __forceinline__ CellPrim<NF> cell_prim(const double (&X)[NF], double gamma) {
 #pragma clang fp contract(off)
   constexpr int ND = NF - 2;
-  const double gm1 = gamma - 1.0;
-  const double rinv = rcp(X[0]);
-  const double un = X[1] * rinv;
+  CellPrim<NF> c;
+  c.rinv = rcp(X[0]);
+  c.un = X[1] * c.rinv;
   double mu = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) mu = fma(X[1 + d], X[1 + d], mu);
-  const double e = fma(-0.5 * rinv, mu, X[NF - 1]);  // internal energy per volume
-  const double p = gm1 * e;
+  c.e = fma(-0.5 * c.rinv, mu, X[NF - 1]);
+  c.p = (gamma - 1.0) * c.e;
+  return c;
+}
+
+template <int NF>
+__device__ __forceinline__ void cell_flux(const double (&X)[NF], const CellPrim<NF>& c, double gamma, double (&F)[NF]) {
+#pragma clang fp contract(off)
+  constexpr int ND = NF - 2;
   F[0] = X[1];
-  F[1] = fma(X[1], un, p);
+  F[1] = fma(X[1], c.un, c.p);
 #pragma unroll
-  for (int t = 1; t < ND; ++t) F[1 + t] = X[1 + t] * un;
-  F[NF - 1] = fma(gm1, e, X[NF - 1]) * un;
-  lam = fabs(un) + sqrt(gamma * p * rinv);
+  for (int t = 1; t < ND; ++t) F[1 + t] = X[1 + t] * c.un;
+  F[NF - 1] = fma(gamma - 1.0, c.e, X[NF - 1]) * c.un;
+}
+
+template <int NF>
+__device__ __forceinline__ double cell_speed(const CellPrim<NF>& c, double gamma) {
+#pragma clang fp contract(off)
+  return fabs(c.un) + sqrt(gamma * c.p * c.rinv);
+}
+
+template <int NF>
+__device__ __forceinline__ void cell_physics(const double (&X)[NF], double gamma, double (&F)[NF], double& lam) {
+  const CellPrim<NF> c = cell_prim<NF>(X, gamma);
+  cell_flux<NF>(X, c, gamma, F);
+  lam = cell_speed<NF>(c, gamma);
 }
 
 // what the Roe average needs of one cell: sqrt(rho), velocity, enthalpy

@@ -255,44 +255,70 @@ void k_sweep_row(SweepParams<NF> p) {
 // (slot of window cell m: (slot0 + m) mod K) and fetches the one new cell of
 // the next face while the current face is computed.
 // ---------------------------------------------------------------------------
+template <int NF>
+struct RoeCarry {
+  RoeIn<NF> r;
+};
+template <>
+struct RoeCarry<1> {};
+
 template <int NF, int K>
 struct RingCells {
-  const double* ring;  // LDS: [K][NF][T] with T threads per block
+  // values per ring slot: the cell's state and, for the Euler equations, its
+  // signal speed (computed once, when the cell enters the window)
+  static constexpr int NR = (NF > 1) ? NF + 1 : NF;
+  const double* ring;  // LDS: [K][NR][T] with T threads per block
   int T, tid, slot0;
   double gamma;
+  RoeCarry<NF>* carry;  // Roe input of the face's right cell, the next face's left
+  __device__ __forceinline__ int slot(int m) const {
+    const int sl = slot0 + m;
+    return sl >= K ? sl - K : sl;
+  }
   __device__ __forceinline__ void load(int m, double (&X)[NF]) const {
-    int sl = slot0 + m;
-    sl = sl >= K ? sl - K : sl;
+    const int sl = slot(m);
 #pragma unroll
-    for (int q = 0; q < NF; ++q) X[q] = ring[(sl * NF + q) * T + tid];
+    for (int q = 0; q < NF; ++q) X[q] = ring[(sl * NR + q) * T + tid];
   }
   __device__ __forceinline__ void cell(int m, double (&X)[NF], double (&F)[NF], double& lam) const {
     load(m, X);
-    cell_physics<NF>(X, gamma, F, lam);
+    cell_flux<NF>(X, cell_prim<NF>(X, gamma), gamma, F);
+    lam = ring[(slot(m) * NR + NF) * T + tid];
   }
   __device__ __forceinline__ void roe(int s, RoeIn<NF>& r) const {
-    double X[NF];
-    load(K / 2 - 1 + s, X);
-    roe_input<NF>(X, gamma, r);
+    if (s == 0) {
+      r = carry->r;
+    } else {
+      double X[NF];
+      load(K / 2, X);
+      roe_input<NF>(X, gamma, r);
+      carry->r = r;
+    }
   }
-  __device__ __forceinline__ double value(int m) const {
-    int sl = slot0 + m;
-    sl = sl >= K ? sl - K : sl;
-    return ring[sl * NF * T + tid];
-  }
+  __device__ __forceinline__ double value(int m) const { return ring[slot(m) * NR * T + tid]; }
 };
+
+// Store a cell into ring slot sl (state, and the signal speed for Euler).
+template <int NF, int K>
+__device__ __forceinline__ void ring_put(double* ring, int T, int tid, int sl, const double (&X)[NF], double gamma) {
+  constexpr int NR = RingCells<NF, K>::NR;
+#pragma unroll
+  for (int q = 0; q < NF; ++q) ring[(sl * NR + q) * T + tid] = X[q];
+  if constexpr (NF > 1) ring[(sl * NR + NF) * T + tid] = cell_speed<NF>(cell_prim<NF>(X, gamma), gamma);
+}
 
 template <int NF, int K>
 struct MarchShape {
-  // lines per block: 4, or 2 when the ring of 4 lines would exceed 64 KiB
-  static constexpr int LINES = (K * NF * 8 * 64 * 4 <= 65536) ? 4 : 2;
+  // lines per block: 4, or 2 when the ring of 4 lines would exceed 80 KiB
+  // (two blocks per CU must fit in its 160 KiB of LDS)
+  static constexpr int LINES = (K * RingCells<NF, K>::NR * 8 * 64 * 4 <= 81920) ? 4 : 2;
 };
 
 template <int NF, int K, int LIM, bool ADAPT>
 __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march(SweepParams<NF> p, int axis) {
   constexpr int LINES = MarchShape<NF, K>::LINES;
   constexpr int T = 64 * LINES;
-  __shared__ double ring[K * NF * T];
+  __shared__ double ring[K * RingCells<NF, K>::NR * T];
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int n_other = (axis == 1) ? p.nz : p.ny;
   // unit u = (line o of the other axis, segment s), o fastest: a 2D grid
@@ -323,10 +349,15 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
   for (int m = 0; m < K; ++m) {
     double X[NF];
     fetch(c_begin - K / 2 + m, X);
-#pragma unroll
-    for (int q = 0; q < NF; ++q) ring[(m * NF + q) * T + tid] = X[q];
+    ring_put<NF, K>(ring, T, tid, m, X, p.fp.gamma);
   }
   int slot0 = 0;
+  RoeCarry<NF> carry;  // the first face's left cell; then handed on face to face
+  if constexpr (NF > 1) {
+    double X[NF];
+    RingCells<NF, K>{ring, T, tid, 0, p.fp.gamma, nullptr}.load(K / 2 - 1, X);
+    roe_input<NF>(X, p.fp.gamma, carry.r);
+  }
   double Fprev[NF];
   for (int t = 0; t <= ncell; ++t) {
     const int j = c_begin + t;
@@ -339,14 +370,13 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
     if (t > 0) epi_load<NF>(p, N, ecell, ein);
     double F[NF];
     {
-      RingCells<NF, K> prov{ring, T, tid, slot0, p.fp.gamma};
+      RingCells<NF, K> prov{ring, T, tid, slot0, p.fp.gamma, &carry};
       prov.load(K / 2 - 1, us);  // cell j - 1 is window cell K/2 - 1 of face j
       uint32_t bits[2][NF];
       face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F, bits);
     }
     if (more) {
-#pragma unroll
-      for (int q = 0; q < NF; ++q) ring[(slot0 * NF + q) * T + tid] = nxt[q];
+      ring_put<NF, K>(ring, T, tid, slot0, nxt, p.fp.gamma);
       slot0 = (slot0 + 1 == K) ? 0 : slot0 + 1;
     }
     if (t > 0) {
