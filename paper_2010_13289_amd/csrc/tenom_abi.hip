@@ -337,6 +337,62 @@ __global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ U
   }
 }
 
+// The same maximum for the Euler equations in ND dimensions: each thread
+// loads four cells before it computes any of them, so that four loads per
+// field are in flight.  The arithmetic per cell is that of k_wave_speed.
+template <int ND>
+__global__ __launch_bounds__(256) void k_wave_speed_euler(const double* __restrict__ U, long N, double gamma,
+                                                          double ix0, double ix1, double ix2,
+                                                          unsigned long long* out) {
+  constexpr int NF = ND + 2, UNR = 4;
+  const double ix[3] = {ix0, ix1, ix2};
+  const long stride = (long)gridDim.x * blockDim.x;
+  double best = 0.0;
+  bool nan = false;
+  for (long i0 = (long)blockIdx.x * blockDim.x + threadIdx.x; i0 < N; i0 += UNR * stride) {
+    double X[UNR][NF];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long i = i0 + u * stride;
+      const long j = i < N ? i : i0;  // past the end: cell i0 again, which leaves the maximum unchanged
+#pragma unroll
+      for (int q = 0; q < NF; ++q) X[u][q] = U[q * N + j];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const double rho = X[u][0];
+      const double ri = 1.0 / rho;
+      double vel[ND], q2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        vel[d] = X[u][1 + d] * ri;
+        q2 += vel[d] * vel[d];
+      }
+      const double p = (gamma - 1.0) * (X[u][NF - 1] - 0.5 * rho * q2);
+      const double c = sqrt(gamma * p * ri);
+      double s = (fabs(vel[0]) + c) * ix[0];
+#pragma unroll
+      for (int d = 1; d < ND; ++d) s += (fabs(vel[d]) + c) * ix[d];
+      if (s != s) nan = true;
+      best = fmax(best, s);
+    }
+  }
+  unsigned long long bits = nan ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(best);
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_down(bits, off, 64);
+    bits = o > bits ? o : bits;
+  }
+  __shared__ unsigned long long part[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = bits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = part[0];
+    for (int w = 1; w < 4; ++w) m = part[w] > m ? part[w] : m;
+    atomicMax(out, m);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ U, long M, unsigned int* out) {
   bool bad = false;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (long)gridDim.x * blockDim.x)
@@ -506,10 +562,18 @@ int tenom_max_wave_speed(const tenom_grid* grid, double gamma, const double* U, 
   if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
   long blocks = (d.N + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_wave_speed, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, grid->ndim, grid->system, gamma,
-                     1.0 / grid->dx[0], grid->ndim > 1 ? 1.0 / grid->dx[1] : 0.0,
-                     grid->ndim > 2 ? 1.0 / grid->dx[2] : 0.0, grid->adv[0], grid->adv[1], grid->adv[2],
-                     (unsigned long long*)buf);
+  const double ix0 = 1.0 / grid->dx[0], ix1 = grid->ndim > 1 ? 1.0 / grid->dx[1] : 0.0,
+               ix2 = grid->ndim > 2 ? 1.0 / grid->dx[2] : 0.0;
+  unsigned long long* mx = (unsigned long long*)buf;
+  if (grid->system == TENOM_SYS_EULER && grid->ndim == 3)
+    hipLaunchKernelGGL(k_wave_speed_euler<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, gamma, ix0, ix1, ix2, mx);
+  else if (grid->system == TENOM_SYS_EULER && grid->ndim == 2)
+    hipLaunchKernelGGL(k_wave_speed_euler<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, gamma, ix0, ix1, ix2, mx);
+  else if (grid->system == TENOM_SYS_EULER)
+    hipLaunchKernelGGL(k_wave_speed_euler<1>, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, gamma, ix0, ix1, ix2, mx);
+  else
+    hipLaunchKernelGGL(k_wave_speed, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, grid->ndim, grid->system, gamma,
+                       ix0, ix1, ix2, grid->adv[0], grid->adv[1], grid->adv[2], mx);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "wave-speed kernel launch");
   unsigned long long bits = 0;
