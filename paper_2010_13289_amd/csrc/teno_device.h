@@ -140,7 +140,7 @@ __device__ __forceinline__ void teno_cutoff(const double (&D)[K - 1], const Teno
     const double s2 = s * s;
     const double s4 = s2 * s2;
     g[k] = s4 * s2;
-    sum = fma(s4, s2, sum);  // the sum takes gamma_k unrounded
+    sum = (k == 0) ? g[0] : fma(s4, s2, sum);  // the sum takes gamma_k unrounded
   }
   const double thr = C_T * sum;
 #pragma unroll
