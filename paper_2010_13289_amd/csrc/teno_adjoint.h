@@ -917,6 +917,17 @@ __device__ __forceinline__ void array_to_bars(const double* o, FaceBars<NF>& b) 
   b.q2 = o[NF + 3];
 }
 
+// Output rule of one adjoint launch, per cell and field of the axis:
+//   out = c src + scale (J^T Lbar)      (src = 0 when NULL)
+// src may be out itself (accumulation) or another array of out's layout (a
+// linear combination of the step adjoint joining the launch); it is read
+// before out is written.
+struct VjpOut {
+  double* out;
+  const double* src;
+  double c, scale;
+};
+
 // Occupancy the tile kernel is compiled for: 3 wavefronts per SIMD (at most
 // 168 VGPRs; three 4-wavefront blocks of 46 KB LDS per CU), measured 20%
 // faster than 2 without spills; the 5-field tile (65 KB LDS, two blocks per
@@ -928,9 +939,9 @@ struct VjpOccupancy {
 
 template <int NF, int K, int LIM, bool ADAPT>
 __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccupancy<NF>::WAVES))) void k_vjp_tile(const double* __restrict__ U,
-                                                       const double* __restrict__ Lbar, double* __restrict__ out,
+                                                       const double* __restrict__ Lbar, VjpOut vo,
                                                        VjpAxis ax, VjpTiles tl, int fld0, int fld1, int fld2,
-                                                       int fld3, int fld4, FaceParams fp, double scale, int acc) {
+                                                       int fld3, int fld4, FaceParams fp) {
   using S = VjpTileShape<NF, K>;
   constexpr int FW = S::FW, P = S::P, AP = S::AP, NB = S::NB, NH = S::NH, H = K / 2;
   __shared__ double sX[NF * P], sF[NF * P], sLam[P], sLb[NF * P], fcs[NF * FW], bS[NF * NB * FW];
@@ -965,15 +976,15 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   const int tid = q * FW + f;
   const int half = f >> 6, lane = f & 63;
 
-  // the owned cell's previous output (accumulate mode), loaded first so that
-  // the load's latency hides behind the kernel instead of ending it
+  // the owned cell's src values of the output rule, loaded first so that
+  // the loads' latency hides behind the kernel instead of ending it
   double prev[NF];
 #pragma unroll
   for (int r = 0; r < NF; ++r) prev[r] = 0.0;
-  if (acc && tid < ncell) {
+  if (vo.src && tid < ncell) {
     const long cell = L.base + (long)(c0 + tid) * L.stride;
 #pragma unroll
-    for (int r = 0; r < NF; ++r) prev[r] = out[(long)fld[r] * N + cell];
+    for (int r = 0; r < NF; ++r) prev[r] = vo.src[(long)fld[r] * N + cell];
   }
 
   // 1. staging; accumulators and the constants' cotangents cleared
@@ -1147,15 +1158,14 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
     cell_physics_vjp<NF>(X, fp.gamma, fs, ls, xs);
     const long cell = L.base + (long)c * L.stride;
 #pragma unroll
-    for (int r = 0; r < NF; ++r) out[(long)fld[r] * N + cell] = prev[r] + scale * xs[r];
+    for (int r = 0; r < NF; ++r) vo.out[(long)fld[r] * N + cell] = vo.c * prev[r] + vo.scale * xs[r];
   }
 }
 
-// out[f][cell] = (acc ? out : 0) + scale * sum of the contributions of every
-// (face, slot) whose stencil cell is `cell`, faces in increasing order.
+// out[f][cell] by the output rule, with s the sum of the contributions of
+// every (face, slot) whose stencil cell is `cell`, faces in increasing order.
 template <int NF, int K>
-__global__ __launch_bounds__(256) void k_gather_vjp(const double* __restrict__ contrib, double* __restrict__ out,
-                                                    VjpAxis ax, double scale, int acc) {
+__global__ __launch_bounds__(256) void k_gather_vjp(const double* __restrict__ contrib, VjpOut vo, VjpAxis ax) {
   const long N = (long)ax.nx * ax.ny * ax.nz;
   const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= N) return;
@@ -1208,7 +1218,7 @@ __global__ __launch_bounds__(256) void k_gather_vjp(const double* __restrict__ c
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     const long o = (long)f * N + cell;
-    out[o] = (acc ? out[o] : 0.0) + scale * s[f];
+    vo.out[o] = (vo.src ? vo.c * vo.src[o] : 0.0) + vo.scale * s[f];
   }
 }
 
@@ -1216,9 +1226,7 @@ struct VjpLaunch {
   const double* U;
   const double* Lbar;
   double* contrib;
-  double* out;
-  double scale;
-  int acc;
+  VjpOut out;
   VjpAxis ax;
   int fld[5];
   FaceParams fp;
@@ -1235,8 +1243,7 @@ hipError_t launch_vjp(const VjpLaunch& a) {
     if (e != hipSuccess) return e;
     const long N = (long)a.ax.nx * a.ax.ny * a.ax.nz;
     const unsigned cb = (unsigned)((N + 255) / 256);
-    hipLaunchKernelGGL((k_gather_vjp<NF, K>), dim3(cb), dim3(256), 0, a.stream, a.contrib, a.out, a.ax, a.scale,
-                       a.acc);
+    hipLaunchKernelGGL((k_gather_vjp<NF, K>), dim3(cb), dim3(256), 0, a.stream, a.contrib, a.out, a.ax);
   } else {
     const long N = (long)a.ax.nx * a.ax.ny * a.ax.nz;
     VjpTiles tl;
@@ -1246,7 +1253,7 @@ hipError_t launch_vjp(const VjpLaunch& a) {
     hipLaunchKernelGGL((k_vjp_tile<NF, K, LIM, ADAPT>), dim3((unsigned)(tl.nlines * ntile)),
                        dim3(VjpTileShape<NF, K>::FW, NF), 0,
                        a.stream, a.U, a.Lbar, a.out, a.ax, tl, a.fld[0], a.fld[1], a.fld[2], a.fld[3], a.fld[4],
-                       a.fp, a.scale, a.acc);
+                       a.fp);
   }
   return hipGetLastError();
 }

@@ -151,9 +151,10 @@ long vjp_faces(const tenom_grid* g, int axis) {
   return d.N / n * (n + (g->bc[axis] == TENOM_BC_TRANSMISSIVE ? 1 : 0));
 }
 
-// out = (acc ? out : 0) + scale * sum over axes of J_axis^T Lbar
+// out by the output rule `base` for the first axis, then += base.scale
+// J_axis^T Lbar for each further axis
 int vjp_axes(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma, const double* U,
-             const double* Lbar, double scale, double* out, bool acc, double* contrib, hipStream_t s) {
+             const double* Lbar, const VjpOut& base, double* contrib, hipStream_t s) {
   bool adaptive;
   const int K = scheme_K(scheme, &adaptive);
   int kind;
@@ -167,9 +168,7 @@ int vjp_axes(const tenom_grid* g, int scheme, int limiter, double C_T, double ga
     L.U = U;
     L.Lbar = Lbar;
     L.contrib = contrib;
-    L.out = out;
-    L.scale = scale;
-    L.acc = (acc || ax > 0) ? 1 : 0;
+    L.out = ax == 0 ? base : VjpOut{base.out, base.out, 1.0, base.scale};
     L.ax.nx = d.nx;
     L.ax.ny = d.ny;
     L.ax.nz = d.nz;
@@ -192,20 +191,23 @@ int vjp_axes(const tenom_grid* g, int scheme, int limiter, double C_T, double ga
   return TENOM_OK;
 }
 
-// out = a x + b y (y may be NULL), elementwise over M values
-__global__ __launch_bounds__(256) void k_axpby(double* __restrict__ out, double a, const double* x, double b,
-                                               const double* y, long M) {
+// out = c0 x + c1 y1 + c2 y2 elementwise over M values, rounded as
+// fma(c2, y2, fma(c1, y1, c0 x))
+__global__ __launch_bounds__(256) void k_comb3(double* out, double c0, const double* x, double c1,
+                                               const double* __restrict__ y1, double c2,
+                                               const double* __restrict__ y2, long M) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (long)gridDim.x * blockDim.x)
-    out[i] = y ? fma(a, x[i], b * y[i]) : a * x[i];
+    out[i] = fma(c2, y2[i], fma(c1, y1[i], c0 * x[i]));
 }
 
-int axpby(double* out, double a, const double* x, double b, const double* y, long M, hipStream_t s) {
+int comb3(double* out, double c0, const double* x, double c1, const double* y1, double c2, const double* y2, long M,
+          hipStream_t s) {
   long blocks = (M + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_axpby, dim3((unsigned)blocks), dim3(256), 0, s, out, a, x, b, y, M);
+  hipLaunchKernelGGL(k_comb3, dim3((unsigned)blocks), dim3(256), 0, s, out, c0, x, c1, y1, c2, y2, M);
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? TENOM_OK : hip_fail(e, "axpby launch");
+  return e == hipSuccess ? TENOM_OK : hip_fail(e, "combination launch");
 }
 
 int march_segment(int n, int nx, int n_other) {
@@ -635,7 +637,8 @@ int tenom_flux_divergence_vjp(const tenom_grid* grid, int scheme, int limiter, d
   if (!isfinite(scale)) return fail(TENOM_EINVAL, "scale must be finite");
   const size_t need = tenom_vjp_workspace_bytes(grid, scheme);
   if (ws_bytes < need) return fail(TENOM_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
-  return vjp_axes(grid, scheme, limiter, C_T, gamma, U, Lbar, scale, Ubar, accumulate != 0, (double*)ws,
+  return vjp_axes(grid, scheme, limiter, C_T, gamma, U, Lbar,
+                  VjpOut{Ubar, accumulate != 0 ? Ubar : nullptr, 1.0, scale}, (double*)ws,
                   (hipStream_t)stream);
 }
 
@@ -667,17 +670,16 @@ int rk3_vjp_core(const tenom_grid* grid, int scheme, int limiter, double C_T, do
                  double* contrib, hipStream_t s) {
   const long M = (long)nfields(grid) * dims(grid).N;
   int rc;
-  // U3 = U/3 + 2/3 (U2 + dt L(U2)):  Ubar2 = 2/3 Ubar3 + 2/3 dt J(U2)^T Ubar3, Ubar_n = Ubar3 / 3
-  if ((rc = axpby(B2, 2.0 / 3.0, Ubar, 0.0, nullptr, M, s))) return rc;
-  if ((rc = vjp_axes(grid, scheme, limiter, C_T, gamma, U2, Ubar, 2.0 / 3.0 * dt, B2, true, contrib, s))) return rc;
-  if ((rc = axpby(Ubar, 1.0 / 3.0, Ubar, 0.0, nullptr, M, s))) return rc;
-  // U2 = 3/4 U + 1/4 (U1 + dt L(U1)):  Ubar1 = 1/4 Ubar2 + 1/4 dt J(U1)^T Ubar2, Ubar_n += 3/4 Ubar2
-  if ((rc = axpby(B1, 0.25, B2, 0.0, nullptr, M, s))) return rc;
-  if ((rc = vjp_axes(grid, scheme, limiter, C_T, gamma, U1, B2, 0.25 * dt, B1, true, contrib, s))) return rc;
-  if ((rc = axpby(Ubar, 0.75, B2, 1.0, Ubar, M, s))) return rc;
-  // U1 = U + dt L(U):  Ubar_n += Ubar1 + dt J(U)^T Ubar1
-  if ((rc = axpby(Ubar, 1.0, B1, 1.0, Ubar, M, s))) return rc;
-  return vjp_axes(grid, scheme, limiter, C_T, gamma, U, B1, dt, Ubar, true, contrib, s);
+  // U3 = U/3 + 2/3 (U2 + dt L(U2)):  Ubar2 = 2/3 Ubar3 + 2/3 dt J(U2)^T Ubar3
+  if ((rc = vjp_axes(grid, scheme, limiter, C_T, gamma, U2, Ubar, VjpOut{B2, Ubar, 2.0 / 3.0, 2.0 / 3.0 * dt}, contrib,
+                     s)))
+    return rc;
+  // U2 = 3/4 U + 1/4 (U1 + dt L(U1)):  Ubar1 = 1/4 Ubar2 + 1/4 dt J(U1)^T Ubar2
+  if ((rc = vjp_axes(grid, scheme, limiter, C_T, gamma, U1, B2, VjpOut{B1, B2, 0.25, 0.25 * dt}, contrib, s)))
+    return rc;
+  // U1 = U + dt L(U):  Ubar_n = Ubar3 / 3 + 3/4 Ubar2 + Ubar1 + dt J(U)^T Ubar1
+  if ((rc = comb3(Ubar, 1.0 / 3.0, Ubar, 0.75, B2, 1.0, B1, M, s))) return rc;
+  return vjp_axes(grid, scheme, limiter, C_T, gamma, U, B1, VjpOut{Ubar, Ubar, 1.0, dt}, contrib, s);
 }
 
 }  // namespace
