@@ -868,14 +868,17 @@ __device__ __forceinline__ void field_rev(const double* sX, const double* sF, in
 //     its two reconstructions; the field values go to LDS;
 //  3. each thread back-projects the face cotangent, reverses its field from
 //     the codes and adds the stencil contributions (row q of L transposed)
-//     to accumulators of its own wavefront (field q, half tile h; in step m
-//     lane l adds to slot l + m, so the lanes of a step meet nowhere); the
-//     fields' cotangents of the eigenvector constants are summed in LDS, one
-//     field after the other;
-//  4. one wavefront per half tile reverses the Roe average once per face;
-//  5. each owned cell sums its slots over fields and half tiles (and, at an
-//     end of a transmissive line, the clamped positions beyond it), applies
-//     its flux Jacobian and signal-speed derivative once and writes out.
+//     to accumulators of its own wavefront (field q; in step m lane l adds
+//     to slot l + m, so the lanes of a step meet nowhere); the fields'
+//     cotangents of the eigenvector constants are summed in LDS, one field
+//     after the other;
+//  4. field 0's wavefront reverses the Roe average once per face, into one
+//     slot per face for its left cell and one for its right cell, while
+//  5a. field 1's wavefront takes one owned cell per lane: it sums the cell's
+//     slots over fields (and, at an end of a transmissive line, the clamped
+//     positions beyond it) and applies the cell's flux Jacobian and
+//     signal-speed derivative once;
+//  5b. it adds the Roe average's slots of the cell and writes out.
 // The order of every sum is fixed.  Blocks on one XCD (blockIdx mod 8) take
 // consecutive lines, so the lines of a strided axis that share cache lines
 // meet in one L2.
@@ -946,6 +949,8 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   constexpr int FW = S::FW, P = S::P, AP = S::AP, NB = S::NB, NH = S::NH, H = K / 2;
   __shared__ double sX[NF * P], sF[NF * P], sLam[P], sLb[NF * P], fcs[NF * FW], bS[NF * NB * FW];
   __shared__ double aX[NF * NH][NF * AP], aF[NF * NH][NF * AP], aL[NF * NH][AP];
+  __shared__ double rXa[NF * AP], rXb[NF * AP];  // the Roe average's cotangents of its left and right cells
+  static_assert(NH == 1, "one wavefront per field: the slot of a face's cell is its lane + offset");
   long g = blockIdx.x;
   const long B = gridDim.x;
   if ((B & 7) == 0) g = (g & 7) * (B >> 3) + (g >> 3);
@@ -976,13 +981,15 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   const int tid = q * FW + f;
   const int half = f >> 6, lane = f & 63;
 
-  // the owned cell's src values of the output rule, loaded first so that
-  // the loads' latency hides behind the kernel instead of ending it
+  // field 1's thread f finishes owned cell c0 + f (step 5); the cell's src
+  // values of the output rule are loaded first so that the loads' latency
+  // hides behind the kernel instead of ending it
+  const bool cell_thread = (q == 1 && f < ncell);
   double prev[NF];
 #pragma unroll
   for (int r = 0; r < NF; ++r) prev[r] = 0.0;
-  if (vo.src && tid < ncell) {
-    const long cell = L.base + (long)(c0 + tid) * L.stride;
+  if (vo.src && cell_thread) {
+    const long cell = L.base + (long)(c0 + f) * L.stride;
 #pragma unroll
     for (int r = 0; r < NF; ++r) prev[r] = vo.src[(long)fld[r] * N + cell];
   }
@@ -1010,6 +1017,7 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
     for (int r = 0; r < NF; ++r) aX[w][r * AP + e] = aF[w][r * AP + e] = 0.0;
     aL[w][e] = 0.0;
   }
+  for (int i = tid; i < NF * AP; i += FW * NF) rXa[i] = rXb[i] = 0.0;
   __syncthreads();
 
   // 2. forward of field q at face f, with its decision codes
@@ -1093,7 +1101,8 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   }
   __syncthreads();
 
-  // 4. the Roe average, once per face (field 0's wavefronts)
+  // 4. the Roe average, once per face (field 0's wavefront), side by side
+  // with 5a. (field 1's wavefront)
   if (q == 0 && wave_live) {
     double o[NB];
 #pragma unroll
@@ -1114,28 +1123,26 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
     FaceState<NF> sr;  // the Roe inputs again (cheaper than keeping them live)
     roe_state<NF>(Xa, Xb, fp.gamma, sr);
     shared_vjp<NF>(Xa, Xb, sr, fp.gamma, bt, xa, xb);
-    // one step: the left cell's part to field 0's slots, the right cell's to
-    // field 1's (both summed in step 5), so no two lanes meet
-    double* hx0 = aX[half];
-    double* hx1 = aX[NH + half];
-    wave_lds_order();
+    // the left cell of face f sits at slot f + H - 1, the right one at f + H:
+    // one lane per slot in each array
     if (live) {
 #pragma unroll
       for (int r = 0; r < NF; ++r) {
-        hx0[r * AP + lane + H - 1] += xa[r];
-        hx1[r * AP + lane + H] += xb[r];
+        rXa[r * AP + lane + H - 1] = xa[r];
+        rXb[r * AP + lane + H] = xb[r];
       }
     }
   }
-  __syncthreads();
 
-  // 5. per owned cell: sum, flux Jacobian, write
-  if (tid < ncell) {
-    const int i = K - 1 + tid;  // slot of cell c0 + tid
-    const int c = c0 + tid;
-    const int lo = (!per && c == 0) ? i - H : i;
-    const int hi = (!per && c == n - 1) ? i + H : i;
-    double xs[NF], fs[NF], ls = 0.0, X[NF];
+  // 5a. per owned cell: the stencil slots of every field, then the flux
+  // Jacobian and the signal speed's derivative
+  const int i = K - 1 + f;  // slot of cell c0 + f
+  const int c = c0 + f;
+  const int lo = (!per && c == 0) ? i - H : i;
+  const int hi = (!per && c == n - 1) ? i + H : i;
+  double xs[NF];
+  if (cell_thread) {
+    double fs[NF], ls = 0.0, X[NF];
 #pragma unroll
     for (int r = 0; r < NF; ++r) {
       xs[r] = fs[r] = 0.0;
@@ -1143,19 +1150,25 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
     }
     for (int k = lo; k <= hi; ++k) {
 #pragma unroll
-      for (int w = 0; w < NH * NF; ++w) {
-        const int e = k - 64 * (w % NH);  // slot k of wavefront w % NH of its field
-        if (e >= 0 && e < AP) {
+      for (int w = 0; w < NF; ++w) {
 #pragma unroll
-          for (int r = 0; r < NF; ++r) {
-            xs[r] += aX[w][r * AP + e];
-            fs[r] += aF[w][r * AP + e];
-          }
-          ls += aL[w][e];
+        for (int r = 0; r < NF; ++r) {
+          xs[r] += aX[w][r * AP + k];
+          fs[r] += aF[w][r * AP + k];
         }
+        ls += aL[w][k];
       }
     }
     cell_physics_vjp<NF>(X, fp.gamma, fs, ls, xs);
+  }
+  __syncthreads();
+
+  // 5b. the Roe average's part, and the write
+  if (cell_thread) {
+    for (int k = lo; k <= hi; ++k) {
+#pragma unroll
+      for (int r = 0; r < NF; ++r) xs[r] += rXa[r * AP + k] + rXb[r * AP + k];
+    }
     const long cell = L.base + (long)c * L.stride;
 #pragma unroll
     for (int r = 0; r < NF; ++r) vo.out[(long)fld[r] * N + cell] = vo.c * prev[r] + vo.scale * xs[r];
