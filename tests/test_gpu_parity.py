@@ -187,6 +187,34 @@ def test_flags_do_not_depend_on_the_limiter(T, orc, scheme):
         assert not mism.any(), f"{int(mism.sum())} flag mismatches outside the band"
 
 
+@pytest.mark.parametrize("scale", [1e60, -1e60, 1e-15])
+@pytest.mark.parametrize("K", [6, 8])
+def test_scalar_faces_at_extreme_magnitudes(T, orc, scale, K):
+    """Scalar data scaled far from O(1): the indicators scale with the data
+    squared (about 1e120 at 1e60, where the GPU's paired reciprocals of the
+    indicator denominators, products of two of them, reach about 1e240); the
+    cutoff decisions are scale-invariant while beta stays far above eps.
+    Faces against the oracle to 1e-12 of the largest magnitude, flags equal
+    outside the band."""
+    grid = dict(ndim=1, n=[300], dx=[0.05], bc=[0], system=0, adv=[1.0])
+    U = W.random_scalar_lines((300,), seed=17, kind="mixed") * scale
+    print(f"[extreme magnitudes] K={K} scale={scale:g}", flush=True)
+    Fo, flo, bdo = orc.reconstruct_faces(U, grid, K, 1, 1e-5, GAMMA, 0)
+    Fg, flg = T.reconstruct_faces(to_dev(U), grid, K, 1, 1e-5, GAMMA, 0, return_flags=True)
+    Fg, flg = to_host(Fg), to_host(flg)
+    assert np.all(np.isfinite(Fg))
+    band = band_faces(bdo)
+    assert_close_fields(Fg, Fo, exclude=band, what=f"scale {scale:g} Fhat")
+    mism = (flg != flo) & ~band[None, None]
+    assert not mism.any(), f"{int(mism.sum())} flag mismatches outside the band"
+    if abs(scale) > 1.0:
+        # the same decisions as on the unscaled data (scale invariance; at
+        # small scales eps is no longer negligible against smooth betas)
+        _, fl1, bd1 = orc.reconstruct_faces(U / scale, grid, K, 1, 1e-5, GAMMA, 0)
+        both = band | band_faces(bd1)
+        assert not ((flg != fl1) & ~both[None, None]).any()
+
+
 def test_constant_state_is_steady(T):
     """A uniform state has zero divergence exactly (every face flux equal)."""
     grid = dict(ndim=3, n=[20, 9, 8], dx=[0.1, 0.1, 0.1], bc=[0, 1, 0], system=1)
