@@ -63,6 +63,7 @@ __global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
   const int nstage = nface + K - 1;
   const Line L{base, 1, n, p.bc};
   const int t = threadIdx.x;
+  __builtin_amdgcn_s_setprio(3);  // high while loads and stores issue, as in the row sweep
 
   for (int c = t; c < nstage; c += TPB) {
     const long cell = cell_at(L, c_begin - K / 2 + c);
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
     stage[(3 * NF) * NC + c] = r.H;
   }
   __syncthreads();
+  __builtin_amdgcn_s_setprio(0);
 
   double F[FPT][NF];
   double us[FPT][NF];
@@ -111,6 +113,7 @@ __global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
     }
   }
   __syncthreads();
+  __builtin_amdgcn_s_setprio(3);
   const double dt = p.dt[prob];
   const double idx = p.inv_dx[prob];
 #pragma unroll

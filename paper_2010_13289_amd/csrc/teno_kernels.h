@@ -192,6 +192,10 @@ void k_sweep_row(SweepParams<NF> p) {
   const long N = (long)p.nx * p.ny * p.nz;
   const Line L{row * p.nx, 1, p.n, p.bc};
   const int t = threadIdx.x;
+  // wave priority: high while the wave issues its global loads and stores
+  // (staging, epilogue), normal while it computes faces, so that a block's
+  // memory phase is not queued behind other blocks' arithmetic on the SIMD
+  __builtin_amdgcn_s_setprio(3);
 
   // stage cells c_begin - K/2 .. c_begin + nface + K/2 - 2
   for (int c = t; c < nstage; c += 256) {
@@ -218,6 +222,7 @@ void k_sweep_row(SweepParams<NF> p) {
   __syncthreads();
 
   double F[NF];
+  __builtin_amdgcn_s_setprio(0);
   if (t < nface) {
     StagedCells<NF, K> prov{stage, NC, t};
     uint32_t bits[2][NF];
@@ -237,6 +242,7 @@ void k_sweep_row(SweepParams<NF> p) {
     for (int q = 0; q < NF; ++q) Fs[q * 257 + t] = F[q];
   }
   __syncthreads();
+  __builtin_amdgcn_s_setprio(3);
   if (t < ncell) {
     const long cell = L.base + c_begin + t;
     EpiIn<NF> ein;
@@ -363,18 +369,21 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
     const int j = c_begin + t;
     const bool more = (t < ncell);
     double nxt[NF];
+    __builtin_amdgcn_s_setprio(3);  // high while loads and stores issue, as in the row sweep
     if (more) fetch(j + K / 2, nxt);  // the new cell of face j + 1
     const long ecell = L.base + (long)(j - 1) * L.stride;  // cell closed by face j
     EpiIn<NF> ein;
     double us[NF];
     if (t > 0) epi_load<NF>(p, N, ecell, ein);
     double F[NF];
+    __builtin_amdgcn_s_setprio(0);
     {
       RingCells<NF, K> prov{ring, T, tid, slot0, p.fp.gamma, &carry};
       prov.load(K / 2 - 1, us);  // cell j - 1 is window cell K/2 - 1 of face j
       uint32_t bits[2][NF];
       face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F, bits);
     }
+    __builtin_amdgcn_s_setprio(3);
     if (more) {
       ring_put<NF, K>(ring, T, tid, slot0, nxt, p.fp.gamma);
       slot0 = (slot0 + 1 == K) ? 0 : slot0 + 1;
