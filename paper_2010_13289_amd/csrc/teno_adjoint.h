@@ -985,6 +985,7 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   // values of the output rule are loaded first so that the loads' latency
   // hides behind the kernel instead of ending it
   const bool cell_thread = (q == 1 && f < ncell);
+  __builtin_amdgcn_s_setprio(3);  // high while loads and stores issue (entry, staging, the write)
   double prev[NF];
 #pragma unroll
   for (int r = 0; r < NF; ++r) prev[r] = 0.0;
@@ -1020,6 +1021,7 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   for (int i = tid; i < NF * AP; i += FW * NF) rXa[i] = rXb[i] = 0.0;
   __syncthreads();
 
+  __builtin_amdgcn_s_setprio(0);
   // 2. forward of field q at face f, with its decision codes
   const int j = c0 - H + 1 + f;  // face of this thread: between positions j-1 and j
   const bool live = f < nface && (per || (j >= 0 && j <= n));
@@ -1164,6 +1166,7 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   __syncthreads();
 
   // 5b. the Roe average's part, and the write
+  __builtin_amdgcn_s_setprio(3);
   if (cell_thread) {
     for (int k = lo; k <= hi; ++k) {
 #pragma unroll
