@@ -76,11 +76,11 @@ BYTES_PER_CELL_STEP = 320
 # by 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB device copy reads
 # as).  They describe the kernels built from the sources whose digest is
 # TRAFFIC_SOURCE_DIGEST and are reported as null for any other build.
-TRAFFIC_SOURCE_DIGEST = "7b84773271140ad92716058cac3f83374d730ef736824bef79131828103543f5"
+TRAFFIC_SOURCE_DIGEST = "0310c2cf0b047d254bef7fbbcae7bd1f630f2de1e4f03df867c9fbc72489523e"
 MEASURED_TRAFFIC = {"sweep_x": 1.3425e9, "sweep_y": 2.0766e9, "sweep_z": 2.5240e9}
 # batched sweep, 4096 problems, averaged over the stages, per tile shape
 # (64x1, 128x1, 128x2, 256x1, 256x2, 512x1): smaller tiles re-read more halo
-MEASURED_TRAFFIC_BATCH = (1.2753e9, 1.1487e9, 1.0866e9, 1.0863e9, 1.0554e9, 1.0550e9)
+MEASURED_TRAFFIC_BATCH = (1.2748e9, 1.1482e9, 1.0861e9, 1.0858e9, 1.0548e9, 1.0545e9)
 
 
 # sources of the adjoint only: the forward and batched sweeps whose traffic
