@@ -4,8 +4,9 @@ One step = one SSP-RK3 step of the 3D Euler equations on a 256^3 periodic
 cube (the Taylor-Green velocity and pressure of Sec. 4.3.1, a planar
 density jump 1 -> 0.125 at x = pi, seeded random-phase velocity
 perturbations), six-point TENO-M with the MP limiter, C_T = 1e-5,
-gamma = 1.4, CFL 0.4: the wave-speed reduction for dt, then 3 stages x
-(x, y, z) sweeps of face reconstructions, divergence and stage update.
+gamma = 1.4, CFL 0.4: the wave-speed reduction and dt on the device
+(tenom_rk3_step_cfl, no host round trip), then 3 stages x (x, y, z) sweeps
+of face reconstructions, divergence and stage update.
 Unit: one face vector (the full 5-component flux at one face, both split
 sides), 3 stages x 3 axes x 256^3 = 150,994,944 per step.
 
@@ -390,8 +391,7 @@ def run_variants(T, U0, grid, n, steps, warmup):
         ws = T.Workspace(grid, scheme, U.device)
 
         def step():
-            rate = T.max_wave_speed(U, grid, GAMMA)
-            T.rk3_step(U, grid, scheme, lim, ct, GAMMA, CFL / rate, workspace=ws)
+            T.rk3_step_cfl(U, grid, scheme, lim, ct, GAMMA, CFL, workspace=ws)
 
         for _ in range(warmup):
             step()
@@ -519,8 +519,8 @@ def main():
         del a, b
 
     def step():
-        rate = T.max_wave_speed(U, grid, GAMMA)
-        T.rk3_step(U, grid, SCHEME, T.LIM_MP, C_T, GAMMA, CFL / rate, workspace=ws)
+        # dt = CFL / (largest signal rate of U), taken on the device
+        T.rk3_step_cfl(U, grid, SCHEME, T.LIM_MP, C_T, GAMMA, CFL, workspace=ws)
 
     for _ in range(args.warmup):
         step()
@@ -565,7 +565,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"3D Euler {n}^3 periodic TGV + density jump + seeded perturbations, "
-                        "TENO6-M-MP, C_T=1e-5, gamma=1.4, CFL 0.4, one SSP-RK3 step",
+                        "TENO6-M-MP, C_T=1e-5, gamma=1.4, CFL 0.4 (dt on the device), one SSP-RK3 step",
             "grid": [n, n, n],
             "scheme": "TENO6-M-MP",
             "face_vectors_per_step": faces_per_step,

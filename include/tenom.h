@@ -168,7 +168,25 @@ int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, 
 int tenom_rk3_step_stages(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
                           double* U, double* U1, double* U2, void* ws, size_t ws_bytes, void* stream);
 
-/* Workspace bytes tenom_rk3_step needs for this grid (0 if invalid). */
+/*
+ * One SSP-RK3 step whose size comes from the CFL condition on the device
+ * (Sec. 4): dt = cfl / R with R = max_cells sum_d (|u_d| + c) / dx_d (scalar
+ * system: sum_d |a_d| / dx_d), the rate tenom_max_wave_speed returns; then
+ * the step of tenom_rk3_step with that dt, to the same bits.  Nothing is
+ * synchronised, copied to the host or allocated, so the call can be captured
+ * in a HIP graph and replayed.
+ *   cfl    : CFL number, finite and > 0 (else TENOM_EINVAL).
+ *   ws     : the workspace of tenom_rk3_step (tenom_workspace_bytes; its
+ *            tail holds the per-block maxima of R and dt).
+ *   dt_out : device address that receives the dt used, or NULL.
+ * A state whose R is NaN, zero or infinite gives a non-finite dt, and the
+ * step then writes non-finite values (tenom_check_finite finds them).
+ */
+int tenom_rk3_step_cfl(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double cfl,
+                       double* U, void* ws, size_t ws_bytes, double* dt_out, void* stream);
+
+/* Workspace bytes tenom_rk3_step, tenom_rk3_step_stages and tenom_rk3_step_cfl
+ * need for this grid (0 if invalid). */
 size_t tenom_workspace_bytes(const tenom_grid* grid, int scheme);
 
 /*

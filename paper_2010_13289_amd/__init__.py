@@ -36,7 +36,7 @@ SYMBOLS = (
     "tenom_batch_set_tile", "tenom_batch_get_tile", "tenom_batch_rk3", "tenom_batch_rk3_graph",
     "tenom_batch_autotune", "tenom_batch_times", "tenom_batch_reset_times",
     "tenom_vjp_workspace_bytes", "tenom_flux_divergence_vjp", "tenom_rk3_vjp_workspace_bytes",
-    "tenom_rk3_step_vjp", "tenom_rk3_step_stages", "tenom_rk3_step_vjp_stages",
+    "tenom_rk3_step_vjp", "tenom_rk3_step_stages", "tenom_rk3_step_vjp_stages", "tenom_rk3_step_cfl",
 )
 
 
@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
         L.tenom_reconstruct_faces.argtypes = [gp, C.c_int, C.c_int, dp, dp, C.c_int, vp, vp, vp, vp]
         L.tenom_flux_divergence.argtypes = [gp, C.c_int, C.c_int, dp, dp, vp, vp, vp]
         L.tenom_rk3_step.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, C.c_size_t, vp]
+        L.tenom_rk3_step_cfl.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, C.c_size_t, vp, vp]
         L.tenom_workspace_bytes.argtypes = [gp, C.c_int]
         L.tenom_workspace_bytes.restype = C.c_size_t
         L.tenom_max_wave_speed.argtypes = [gp, dp, vp, C.POINTER(C.c_double), vp]
@@ -249,6 +250,27 @@ def rk3_step(U, grid, scheme: int, limiter: int, C_T: float, gamma: float, dt: f
         p1, p2 = _state(stages[0], g, "U1"), _state(stages[1], g, "U2")
         _check(lib().tenom_rk3_step_stages(C.byref(gc), scheme, limiter, C_T, gamma, dt, ptr, p1, p2, ws.ptr,
                                            ws.nbytes, _stream(stream)))
+    return U
+
+
+def rk3_step_cfl(U, grid, scheme: int, limiter: int, C_T: float, gamma: float, cfl: float,
+                 workspace: Workspace | None = None, stream=None, dt_out=None):
+    """One SSP-RK3 step in place on U with dt = cfl / max_wave_speed(U)
+    taken on the device (tenom_rk3_step_cfl): no synchronisation, so it can
+    be captured in a graph.  dt_out: optional 1-element float64 device
+    tensor that receives the dt used.  Returns U."""
+    g = Grid.of(grid)
+    ptr = _state(U, g)
+    ws = workspace if workspace is not None else Workspace(g, scheme, U.device)
+    dptr = None
+    if dt_out is not None:
+        import torch
+        if not (dt_out.is_cuda and dt_out.dtype == torch.float64 and dt_out.numel() >= 1 and dt_out.is_contiguous()):
+            raise TenomError(EINVAL, "dt_out must be a contiguous float64 device tensor with at least one element")
+        dptr = C.c_void_p(dt_out.data_ptr())
+    gc = g.to_c()
+    _check(lib().tenom_rk3_step_cfl(C.byref(gc), scheme, limiter, C_T, gamma, cfl, ptr, ws.ptr, ws.nbytes, dptr,
+                                    _stream(stream)))
     return U
 
 

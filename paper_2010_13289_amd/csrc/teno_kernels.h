@@ -40,6 +40,7 @@ struct SweepParams {
   const double* U0;  // RK: U^n
   double* Uout;      // RK: output state
   double a, b, dt;   // RK coefficients
+  const double* dtp; // if not NULL: dt is read from this device address instead
   int mode;
   int nx, ny, nz;    // grid extents (1 for unused axes)
   int n;             // cells along the sweep axis
@@ -72,6 +73,7 @@ __device__ __forceinline__ void epi_load(const SweepParams<NF>& p, long N, long 
 template <int NF>
 __device__ __forceinline__ void epi_store(const SweepParams<NF>& p, long N, long cell, const double (&div)[NF],
                                           const EpiIn<NF>& in, const double (&us)[NF]) {
+  const double dt = p.dtp ? *p.dtp : p.dt;
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
     const long o = (long)p.fld[q] * N + cell;
@@ -81,7 +83,7 @@ __device__ __forceinline__ void epi_store(const SweepParams<NF>& p, long N, long
       p.R[o] = in.r[q] + div[q];
     } else {
       const double rhs = (p.mode == EPI_RK) ? in.r[q] + div[q] : div[q];
-      const double v = fma(p.dt, rhs, us[q]);
+      const double v = fma(dt, rhs, us[q]);
       p.Uout[o] = (p.a != 0.0) ? fma(p.a, in.u0[q], p.b * v) : p.b * v;
     }
   }
@@ -419,6 +421,7 @@ struct SweepLaunch {
   const double* U0;
   double* Uout;
   double a, b, dt;
+  const double* dtp;  // device dt (NULL: use dt)
   int mode;
   int nx, ny, nz, bc;
   double inv_dx;
@@ -447,6 +450,7 @@ hipError_t launch_sweep(const SweepLaunch& a) {
   p.a = a.a;
   p.b = a.b;
   p.dt = a.dt;
+  p.dtp = a.dtp;
   p.mode = a.mode;
   p.nx = a.nx;
   p.ny = a.ny;

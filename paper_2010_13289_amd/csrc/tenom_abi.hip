@@ -233,7 +233,8 @@ int march_segment(int n, int nx, int n_other) {
 // Launch one sweep of `axis` with the given epilogue.  In the RK modes the
 // stage state U_s of the update is U, the state the stencils read.
 int sweep(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma, int axis, const double* U,
-          double* R, const double* U0, double* Uout, double a, double b, double dt, int mode, hipStream_t stream) {
+          double* R, const double* U0, double* Uout, double a, double b, double dt, int mode, hipStream_t stream,
+          const double* dtp = nullptr) {
   FacesFn ff;
   SweepFn sf;
   const int nf = nfields(g);
@@ -253,6 +254,7 @@ int sweep(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma
   L.a = a;
   L.b = b;
   L.dt = dt;
+  L.dtp = dtp;
   L.mode = mode;
   L.nx = d.nx;
   L.ny = d.ny;
@@ -298,7 +300,8 @@ int reduction_buffer(void** out) {
 // non-negative double (NaN patterns order above every finite value)
 __global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ U, long N, int ndim, int system,
                                                     double gamma, double ix0, double ix1, double ix2, double a0,
-                                                    double a1, double a2, unsigned long long* out) {
+                                                    double a1, double a2, unsigned long long* out,
+                                                    unsigned long long* part_out) {
   double best = 0.0;
   bool nan = false;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
@@ -335,7 +338,10 @@ __global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ U
   if (threadIdx.x == 0) {
     unsigned long long m = part[0];
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = part[w] > m ? part[w] : m;
-    atomicMax(out, m);
+    if (part_out)
+      part_out[blockIdx.x] = m;
+    else
+      atomicMax(out, m);
   }
 }
 
@@ -345,7 +351,7 @@ __global__ __launch_bounds__(256) void k_wave_speed(const double* __restrict__ U
 template <int ND>
 __global__ __launch_bounds__(256) void k_wave_speed_euler(const double* __restrict__ U, long N, double gamma,
                                                           double ix0, double ix1, double ix2,
-                                                          unsigned long long* out) {
+                                                          unsigned long long* out, unsigned long long* part_out) {
   constexpr int NF = ND + 2, UNR = 4;
   const double ix[3] = {ix0, ix1, ix2};
   const long stride = (long)gridDim.x * blockDim.x;
@@ -391,8 +397,66 @@ __global__ __launch_bounds__(256) void k_wave_speed_euler(const double* __restri
   if (threadIdx.x == 0) {
     unsigned long long m = part[0];
     for (int w = 1; w < 4; ++w) m = part[w] > m ? part[w] : m;
-    atomicMax(out, m);
+    if (part_out)
+      part_out[blockIdx.x] = m;
+    else
+      atomicMax(out, m);
   }
+}
+
+// dt = cfl / (largest signal rate) from the per-block maxima of the rate
+// kernels (their ordered bit patterns), by one block of 256 threads.  A NaN
+// rate orders above every finite one and gives dt = NaN; a zero rate gives
+// dt = inf.
+__global__ __launch_bounds__(256) void k_cfl_dt(const unsigned long long* __restrict__ part, int nparts, double cfl,
+                                                double* dt_ws, double* dt_out) {
+  unsigned long long bits = 0;
+  for (int i = threadIdx.x; i < nparts; i += 256) bits = part[i] > bits ? part[i] : bits;
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_down(bits, off, 64);
+    bits = o > bits ? o : bits;
+  }
+  __shared__ unsigned long long w4[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) w4[wid] = bits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = w4[0];
+    for (int w = 1; w < 4; ++w) m = w4[w] > m ? w4[w] : m;
+    const double dt = cfl / __longlong_as_double((long long)m);
+    *dt_ws = dt;
+    if (dt_out) *dt_out = dt;
+  }
+}
+
+// Grid of the rate kernels: at most kRateBlocks blocks of 256 threads.
+constexpr long kRateBlocks = 4096;
+
+long rate_blocks(long N) {
+  long blocks = (N + 255) / 256;
+  return blocks > kRateBlocks ? kRateBlocks : blocks;
+}
+
+// Launch the rate kernel of the grid's system: per-block maxima into
+// part_out, or (part_out NULL) the atomic maximum into out.
+hipError_t launch_rate(const tenom_grid* grid, double gamma, const double* U, long N, unsigned long long* out,
+                       unsigned long long* part_out, hipStream_t s) {
+  const long blocks = rate_blocks(N);
+  const double ix0 = 1.0 / grid->dx[0], ix1 = grid->ndim > 1 ? 1.0 / grid->dx[1] : 0.0,
+               ix2 = grid->ndim > 2 ? 1.0 / grid->dx[2] : 0.0;
+  if (grid->system == TENOM_SYS_EULER && grid->ndim == 3)
+    hipLaunchKernelGGL(k_wave_speed_euler<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, N, gamma, ix0, ix1, ix2, out,
+                       part_out);
+  else if (grid->system == TENOM_SYS_EULER && grid->ndim == 2)
+    hipLaunchKernelGGL(k_wave_speed_euler<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, N, gamma, ix0, ix1, ix2, out,
+                       part_out);
+  else if (grid->system == TENOM_SYS_EULER)
+    hipLaunchKernelGGL(k_wave_speed_euler<1>, dim3((unsigned)blocks), dim3(256), 0, s, U, N, gamma, ix0, ix1, ix2, out,
+                       part_out);
+  else
+    hipLaunchKernelGGL(k_wave_speed, dim3((unsigned)blocks), dim3(256), 0, s, U, N, grid->ndim, grid->system, gamma,
+                       ix0, ix1, ix2, grid->adv[0], grid->adv[1], grid->adv[2], out, part_out);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ U, long M, unsigned int* out) {
@@ -482,19 +546,26 @@ int tenom_flux_divergence(const tenom_grid* grid, int scheme, int limiter, doubl
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static size_t state_bytes(const tenom_grid* grid) {
+  return align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
+}
+
+// bytes after the three states: the rate kernels' per-block maxima and dt
+static size_t cfl_tail_bytes() { return align256((size_t)(kRateBlocks + 1) * sizeof(double)); }
+
 size_t tenom_workspace_bytes(const tenom_grid* grid, int scheme) {
   bool adaptive;
   const int K = scheme_K(scheme, &adaptive);
   if (!K || check_grid(grid, K) != TENOM_OK) return 0;
-  const size_t state = align256((size_t)nfields(grid) * (size_t)dims(grid).N * sizeof(double));
-  return 3 * state;  // divergence accumulator R, stage states U1 and U2
+  // divergence accumulator R, stage states U1 and U2, then the CFL tail
+  return 3 * state_bytes(grid) + cfl_tail_bytes();
 }
 
 namespace {
 
 // The three stages of one SSP-RK3 step: U1, U2 written, U updated in place.
 int rk3_stages(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma, double dt, double* U, double* R,
-               double* U1, double* U2, hipStream_t s) {
+               double* U1, double* U2, hipStream_t s, const double* dtp = nullptr) {
   const int nd = g->ndim;
   // (a, b) of U_out = a U^n + b (U_s + dt L(U_s)), stage inputs and outputs
   const double A[3] = {0.0, 0.75, 1.0 / 3.0};
@@ -505,7 +576,7 @@ int rk3_stages(const tenom_grid* g, int scheme, int limiter, double C_T, double 
     for (int ax = 0; ax < nd; ++ax) {
       const bool last = (ax == nd - 1);
       int mode = last ? (nd == 1 ? EPI_RK1 : EPI_RK) : (ax == 0 ? EPI_STORE : EPI_ACCUM);
-      const int rc = sweep(g, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uo[st], A[st], B[st], dt, mode, s);
+      const int rc = sweep(g, scheme, limiter, C_T, gamma, ax, Uin[st], R, U, Uo[st], A[st], B[st], dt, mode, s, dtp);
       if (rc) return rc;
     }
   }
@@ -531,11 +602,34 @@ int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, 
   g_err[0] = 0;
   const int rc = rk3_step_checks(grid, scheme, limiter, C_T, gamma, dt, U, ws, ws_bytes);
   if (rc) return rc;
-  const size_t state = tenom_workspace_bytes(grid, scheme) / 3;
+  const size_t state = state_bytes(grid);
   double* R = (double*)ws;
   double* U1 = (double*)((char*)ws + state);
   double* U2 = (double*)((char*)ws + 2 * state);
   return rk3_stages(grid, scheme, limiter, C_T, gamma, dt, U, R, U1, U2, (hipStream_t)stream);
+}
+
+int tenom_rk3_step_cfl(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double cfl,
+                       double* U, void* ws, size_t ws_bytes, double* dt_out, void* stream) {
+  g_err[0] = 0;
+  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(TENOM_EINVAL, "cfl must be finite and > 0 (got %g)", cfl);
+  // dt is formed on the device; 1.0 stands in for it in the host checks
+  const int rc = rk3_step_checks(grid, scheme, limiter, C_T, gamma, 1.0, U, ws, ws_bytes);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t state = state_bytes(grid);
+  double* R = (double*)ws;
+  double* U1 = (double*)((char*)ws + state);
+  double* U2 = (double*)((char*)ws + 2 * state);
+  unsigned long long* part = (unsigned long long*)((char*)ws + 3 * state);
+  double* dt_dev = (double*)(part + kRateBlocks);
+  const long N = dims(grid).N;
+  hipError_t e = launch_rate(grid, gamma, U, N, nullptr, part, s);
+  if (e != hipSuccess) return hip_fail(e, "wave-speed kernel launch");
+  hipLaunchKernelGGL(k_cfl_dt, dim3(1), dim3(256), 0, s, part, (int)rate_blocks(N), cfl, dt_dev, dt_out);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "step-size kernel launch");
+  return rk3_stages(grid, scheme, limiter, C_T, gamma, 0.0, U, R, U1, U2, s, dt_dev);
 }
 
 int tenom_rk3_step_stages(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
@@ -562,21 +656,7 @@ int tenom_max_wave_speed(const tenom_grid* grid, double gamma, const double* U, 
   const Dims d = dims(grid);
   hipError_t e = hipMemsetAsync(buf, 0, 8, s);
   if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
-  long blocks = (d.N + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  const double ix0 = 1.0 / grid->dx[0], ix1 = grid->ndim > 1 ? 1.0 / grid->dx[1] : 0.0,
-               ix2 = grid->ndim > 2 ? 1.0 / grid->dx[2] : 0.0;
-  unsigned long long* mx = (unsigned long long*)buf;
-  if (grid->system == TENOM_SYS_EULER && grid->ndim == 3)
-    hipLaunchKernelGGL(k_wave_speed_euler<3>, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, gamma, ix0, ix1, ix2, mx);
-  else if (grid->system == TENOM_SYS_EULER && grid->ndim == 2)
-    hipLaunchKernelGGL(k_wave_speed_euler<2>, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, gamma, ix0, ix1, ix2, mx);
-  else if (grid->system == TENOM_SYS_EULER)
-    hipLaunchKernelGGL(k_wave_speed_euler<1>, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, gamma, ix0, ix1, ix2, mx);
-  else
-    hipLaunchKernelGGL(k_wave_speed, dim3((unsigned)blocks), dim3(256), 0, s, U, d.N, grid->ndim, grid->system, gamma,
-                       ix0, ix1, ix2, grid->adv[0], grid->adv[1], grid->adv[2], mx);
-  e = hipGetLastError();
+  e = launch_rate(grid, gamma, U, d.N, (unsigned long long*)buf, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "wave-speed kernel launch");
   unsigned long long bits = 0;
   e = hipMemcpyAsync(&bits, buf, 8, hipMemcpyDeviceToHost, s);

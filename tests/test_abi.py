@@ -82,7 +82,8 @@ def test_pointer_and_axis_errors(lib):
 def test_rk3_workspace_and_dt_errors(lib):
     g = grid()
     need = lib.tenom_workspace_bytes(C.byref(g), 6)
-    assert need == 3 * 5 * 16 ** 3 * 8
+    # three states, then the step-size tail: 4096 per-block maxima and dt, 256-byte aligned
+    assert need == 3 * 5 * 16 ** 3 * 8 + 33024
     ws = C.c_void_p(0x10000)
     assert lib.tenom_rk3_step(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, ws, need - 1, None) == T.EWORKSPACE
     assert lib.tenom_rk3_step(C.byref(g), 6, 1, 1e-5, 1.4, 0.0, DUMMY, ws, need, None) == T.EINVAL
@@ -111,6 +112,23 @@ def test_stage_entry_errors(lib):
     assert vjp(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, U1, U2, U1, ws, vneed, None) == T.EINVAL
     assert vjp(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, U1, U2, DUMMY, ws, vneed, None) == T.EINVAL
     assert vjp(C.byref(g), 6, 1, 1e-5, 1.4, 0.01, DUMMY, U1, U2, Ub, ws, vneed - 1, None) == T.EWORKSPACE
+
+
+def test_cfl_step_errors(lib):
+    """tenom_rk3_step_cfl rejects a bad CFL number, missing pointers and a
+    short workspace before any launch; its workspace is tenom_rk3_step's,
+    which holds three states and the step-size tail."""
+    g = grid()
+    need = lib.tenom_workspace_bytes(C.byref(g), 6)
+    ws = C.c_void_p(0x10000)
+    step = lib.tenom_rk3_step_cfl
+    for cfl in (0.0, -0.4, float("nan"), float("inf")):
+        assert step(C.byref(g), 6, 1, 1e-5, 1.4, cfl, DUMMY, ws, need, None, None) == T.EINVAL, cfl
+    assert step(C.byref(g), 6, 1, 1e-5, 1.4, 0.4, None, ws, need, None, None) == T.EINVAL
+    assert step(C.byref(g), 6, 1, 1e-5, 1.4, 0.4, DUMMY, None, need, None, None) == T.EINVAL
+    assert step(C.byref(g), 6, 1, 1e-5, 1.4, 0.4, DUMMY, C.c_void_p(0x10008), need, None, None) == T.EINVAL
+    assert step(C.byref(g), 6, 1, 1e-5, 1.4, 0.4, DUMMY, ws, need - 1, None, None) == T.EWORKSPACE
+    assert step(C.byref(g), 6, 9, 1e-5, 1.4, 0.4, DUMMY, ws, need, None, None) == T.EUNSUPPORTED
 
 
 def test_scheme_and_limiter_ids(lib):
