@@ -69,11 +69,16 @@ __device__ __forceinline__ void epi_load(const SweepParams<NF>& p, long N, long 
   }
 }
 
+// The step size of the RK modes, read once per thread.
+template <int NF>
+__device__ __forceinline__ double epi_dt(const SweepParams<NF>& p) {
+  return p.dtp ? *p.dtp : p.dt;
+}
+
 // us: the cell's stage state (rotated components), only used by RK modes
 template <int NF>
 __device__ __forceinline__ void epi_store(const SweepParams<NF>& p, long N, long cell, const double (&div)[NF],
-                                          const EpiIn<NF>& in, const double (&us)[NF]) {
-  const double dt = p.dtp ? *p.dtp : p.dt;
+                                          const EpiIn<NF>& in, const double (&us)[NF], double dt) {
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
     const long o = (long)p.fld[q] * N + cell;
@@ -253,7 +258,7 @@ void k_sweep_row(SweepParams<NF> p) {
     double div[NF];
 #pragma unroll
     for (int q = 0; q < NF; ++q) div[q] = (Fs[q * 257 + t] - Fs[q * 257 + r]) * p.inv_dx;
-    epi_store<NF>(p, N, cell, div, ein, us);
+    epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
   }
 }
 
@@ -366,6 +371,12 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
     RingCells<NF, K>{ring, T, tid, 0, p.fp.gamma, nullptr}.load(K / 2 - 1, X);
     roe_input<NF>(X, p.fp.gamma, carry.r);
   }
+  // six points: dt read once and held in a vector register.  The loop is
+  // short of scalar registers, and a scalar copy spills into lanes that every
+  // iteration reads back; the eight-point loop, short of vector registers
+  // instead, reads it at each store.
+  double dt = epi_dt(p);
+  if constexpr (K == 6) asm volatile("" : "+v"(dt));
   double Fprev[NF];
   for (int t = 0; t <= ncell; ++t) {
     const int j = c_begin + t;
@@ -394,7 +405,7 @@ __global__ __launch_bounds__((64 * MarchShape<NF, K>::LINES)) void k_sweep_march
       double div[NF];
 #pragma unroll
       for (int q = 0; q < NF; ++q) div[q] = (Fprev[q] - F[q]) * p.inv_dx;
-      epi_store<NF>(p, N, ecell, div, ein, us);
+      epi_store<NF>(p, N, ecell, div, ein, us, K == 6 ? dt : epi_dt(p));
     }
 #pragma unroll
     for (int q = 0; q < NF; ++q) Fprev[q] = F[q];
