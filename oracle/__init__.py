@@ -3,7 +3,7 @@
 Only the test suite, the smoke check and the CPU-baseline leg of the
 benchmark may import this package.  It wraps ``libtenom_oracle.so``, built
 from ``tenom_oracle.c`` by :func:`build`, with ctypes, and adds the exact
-Riemann solver used to judge shock-tube runs (``oracle.exact_riemann``).
+Riemann solver used to check shock-tube runs (``oracle.exact_riemann``).
 It shares no code with the HIP library.
 """
 from __future__ import annotations

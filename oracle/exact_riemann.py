@@ -1,6 +1,6 @@
 """Exact solution of the 1D Riemann problem for the ideal-gas Euler equations.
 
-Test infrastructure: it judges shock-tube runs (the Sod and Lax problems of
+Test infrastructure: it checks shock-tube runs (the Sod and Lax problems of
 Sec. 4.2.1 and the seeded Riemann states) and is not part of the scheme.
 The classical construction: the star-region pressure p* solves
 f_L(p) + f_R(p) + (u_R - u_L) = 0, where f_K is the shock (Rankine-Hugoniot)
