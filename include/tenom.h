@@ -41,7 +41,7 @@ extern "C" {
 
 /* ---- return codes ----------------------------------------------------- */
 #define TENOM_OK 0
-#define TENOM_EINVAL (-1)      /* null pointer, ndim not in {1,2,3}, an used
+#define TENOM_EINVAL (-1)      /* null pointer, ndim not in {1,2,3}, a used
                                   axis with fewer than K cells, axis >= ndim,
                                   C_T < 0 or NaN (or > 1/(K-2) for classic
                                   TENO), gamma <= 1 (Euler), dt <= 0 or
