@@ -789,8 +789,8 @@ __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wavefront accumulators of one field and half tile: slot lane + m of
-// each [NF][AP] array collects stencil cell m of the face of `lane`.
+// Per-wavefront accumulators of one field: slot lane + m of each [NF][AP]
+// array collects stencil cell m of the face of `lane`.
 struct FieldAcc {
   double* x;    // cotangent of the cell state (direct part)
   double* f;    // cotangent of the cell's physical flux
