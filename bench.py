@@ -45,12 +45,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import workloads as W  # noqa: E402  (seeded inputs; no scheme arithmetic)
+
 METRIC = "face-reconstructions/s + % HBM roofline (fwd, fwd+adjoint, batched vs plain)"
 N = 256
 GAMMA = 1.4
 C_T = 1e-5
 SCHEME = 6
-CFL = 0.4
+CFL = W.CFL
 
 # MI355X published peaks
 PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 FP64 lanes x 2 (FMA) x 2.4 GHz
@@ -150,7 +152,6 @@ def run_adjoint(args):
     import torch
 
     import paper_2010_13289_amd as T
-    import workloads as W
     n, steps, ck = args.adj_n, args.adj_steps, 20
     U0h, dx = W.density_modes_2d(n, seed=5)
     T0h, _ = W.density_modes_2d(n, seed=6)
@@ -254,7 +255,6 @@ def run_batched(args):
     import torch
 
     import paper_2010_13289_amd as T
-    import workloads as W
     sizes = W.batched_riemann_sizes()
     parts, dx = [], []
     for p, n in enumerate(sizes):
@@ -469,7 +469,6 @@ def main():
     import torch
 
     import paper_2010_13289_amd as T
-    import workloads as W
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)

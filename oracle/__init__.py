@@ -48,7 +48,7 @@ class Trace(C.Structure):
                 ("delta", C.c_int * 6), ("band", C.c_int * 6), ("fmin", C.c_double),
                 ("fmax", C.c_double), ("ftvd", C.c_double), ("fM", C.c_double * 6),
                 ("out", C.c_double), ("eta", C.c_double), ("m", C.c_double), ("ct", C.c_double),
-                ("ct_band", C.c_int)]
+                ("ct_band", C.c_int), ("status", C.c_int)]
 
 
 _lib = None
@@ -63,6 +63,8 @@ def lib():
         dp, u8p, lp = C.POINTER(C.c_double), C.POINTER(C.c_uint8), C.POINTER(C.c_long)
         gp = C.POINTER(_Grid)
         L.or_init.restype = C.c_int
+        L.or_param.argtypes = [C.c_char_p]
+        L.or_param.restype = C.c_double
         L.or_get_weights.argtypes = [C.c_int, dp]
         L.or_get_poly_face.argtypes = [C.c_int, C.c_int, dp]
         L.or_beta_stencil.argtypes = [C.c_int, C.c_int, dp]
@@ -162,9 +164,25 @@ def _state(U, grid):
     return U
 
 
+ENONFINITE = -5  # a sum of gamma_k overflowed (Eq. normalize undefined)
+
+
+class NonFiniteIndicator(RuntimeError):
+    """The literal gamma_k of Eq. measureTENO overflowed somewhere."""
+
+
 def _chk(rc, what):
+    if rc == ENONFINITE:
+        raise NonFiniteIndicator(f"oracle {what}: the sum of gamma_k is not finite")
     if rc != 0:
         raise RuntimeError(f"oracle {what} failed with {rc}")
+
+
+def param(name: str) -> float:
+    """A constant the oracle uses, by the name of the paper's parameter
+    (C, q, epsilon, mp_alpha, mp_beta, tvd5_alpha, va_kappa, ren_xi, ren_cr,
+    adapt_alpha1, adapt_alpha2); NaN for an unknown name."""
+    return lib().or_param(name.encode())
 
 
 # ---------------------------------------------------------------------------

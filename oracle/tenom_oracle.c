@@ -56,8 +56,10 @@ static const double OR_C = 1.0;
 static const double OR_Q = 6.0;
 static const double OR_EPS = 1e-40;
 
-/* Eq. upper_limiter: alpha = 1.25; Eq. large_curvature: beta = 4 */
+/* Eq. upper_limiter: alpha = 1.25; Eq. large_curvature: beta = 4 (the
+ * recommended value; Secs. 4.2.5 and 4.4 also run beta = 2 and 1) */
 static const double OR_MP_ALPHA = 1.25;
+static const double OR_MP_BETA = 4.0;
 /* Eq. high order TVD: alpha = 2 */
 static const double OR_TVD5_ALPHA = 2.0;
 /* Sec. 3.2.1: kappa = 1/3 restores third order for the Van Albada flux */
@@ -73,6 +75,31 @@ static const double OR_ADAPT_A2 = 3.5;
 
 /* Relative width of the cutoff band reported next to the flags. */
 static const double OR_BAND = 1e-10;
+
+/* Status of a reconstruction whose gamma sum is not finite (Eq. normalize
+ * is then undefined); the whole-grid entry points return it as well. */
+#define OR_ENONFINITE (-5)
+
+/* The printed constants by name, so that a test can hold them against the
+ * paper's text; NaN for an unknown name. */
+double or_param(const char* name) {
+    const struct { const char* name; double value; } tab[] = {
+        {"C", OR_C},
+        {"q", OR_Q},
+        {"epsilon", OR_EPS},
+        {"mp_alpha", OR_MP_ALPHA},
+        {"mp_beta", OR_MP_BETA},
+        {"tvd5_alpha", OR_TVD5_ALPHA},
+        {"va_kappa", OR_VA_KAPPA},
+        {"ren_xi", OR_REN_XI},
+        {"ren_cr", OR_REN_CR},
+        {"adapt_alpha1", OR_ADAPT_A1},
+        {"adapt_alpha2", OR_ADAPT_A2},
+    };
+    for (size_t i = 0; i < sizeof(tab) / sizeof(tab[0]); i++)
+        if (strcmp(tab[i].name, name) == 0) return tab[i].value;
+    return NAN;
+}
 
 /* Scheme identifiers: the number of points K, optionally with the adaptive
  * cutoff flag (the eight-point TENO8A scheme of Sec. 2.4). */
@@ -454,6 +481,7 @@ typedef struct {
     double m;        /* adaptive cutoff: m */
     double ct;       /* the C_T actually used */
     int ct_band;     /* adaptive cutoff: beta within 1e-10 of an integer */
+    int status;      /* 0, or OR_ENONFINITE when sum_k gamma_k is not finite */
 } or_trace;
 
 /* Eqs. shock_indicator and cut-off_adjust: the cutoff of one face from
@@ -516,6 +544,14 @@ double or_teno_m(int scheme, int lim, double C_T, const double* v, or_trace* tr)
         tr->gam[k] = pow(OR_C + tr->tau / (tr->beta[k] + OR_EPS), OR_Q);
         sum += tr->gam[k];
     }
+    /* The literal gamma_k overflows once tau / (beta_k + eps) exceeds about
+     * 1e51 (a jump of about 1e6 beside exactly constant data); chi_k is then
+     * undefined, so the reconstruction reports it instead of guessing. */
+    if (!isfinite(sum)) {
+        tr->status = OR_ENONFINITE;
+        tr->out = NAN;
+        return NAN;
+    }
     /* Eq. normalize and Eq. cut-off */
     for (int k = 0; k < nk; k++) {
         tr->chi[k] = tr->gam[k] / sum;
@@ -535,10 +571,10 @@ double or_teno_m(int scheme, int lim, double C_T, const double* v, or_trace* tr)
         tr->out = acc;
         return acc;
     }
-    int is_mp = (lim == OR_LIM_MP || lim >= OR_LIM_MP_M4_B2);
+    int is_mp = (lim == OR_LIM_MP || (lim >= OR_LIM_MP_M4_B2 && lim <= OR_LIM_MP_MM_B1));
     if (is_mp) {
         int curv = (lim == OR_LIM_MP || lim == OR_LIM_MP_M4_B2) ? 0 : 1;
-        double bet = (lim == OR_LIM_MP || lim == OR_LIM_MP_MM_B4) ? 4.0
+        double bet = (lim == OR_LIM_MP || lim == OR_LIM_MP_MM_B4) ? OR_MP_BETA
                      : (lim == OR_LIM_MP_MM_B1) ? 1.0 : 2.0;
         or_mp_bounds(fm2, fm1, f0, fp1, fp2, curv, bet, &tr->fmin, &tr->fmax);
     } else if (lim == OR_LIM_TVD_MINMOD) {
@@ -754,6 +790,7 @@ static int or_face_flux(const or_grid* g, const or_scheme* sc, const or_state* s
         for (int m = 0; m < K; m++) mir[m] = gm[c][K - 1 - m];
         double fplus = or_teno_m(sc->K, sc->lim, sc->C_T, gp[c], &tp);
         double fminus = or_teno_m(sc->K, sc->lim, sc->C_T, mir, &tm);
+        if (tp.status || tm.status) return OR_ENONFINITE;
         fc[c] = fplus + fminus;
         if (flags || band) {
             uint8_t bp = 0, bm = 0, np = 0, nm = 0;
@@ -797,8 +834,9 @@ static int or_dudt_cell(const or_grid* g, const or_scheme* sc, const or_state* s
         uint8_t br[10], bl[10];
         int pl[3] = {p[0], p[1], p[2]};
         pl[ax] -= 1;
-        if (or_face_flux(g, sc, s, ax, p, Fr, NULL, br) != 0) return -1;
-        if (or_face_flux(g, sc, s, ax, pl, Fl, NULL, bl) != 0) return -1;
+        int rc = or_face_flux(g, sc, s, ax, p, Fr, NULL, br);
+        if (rc == 0) rc = or_face_flux(g, sc, s, ax, pl, Fl, NULL, bl);
+        if (rc) return rc;
         if (bandhit)
             for (int t = 0; t < 2 * nf; t++) *bandhit += (br[t] != 0) + (bl[t] != 0);
         for (int f = 0; f < nf; f++) dU[f] = dU[f] - (Fr[f] - Fl[f]) / g->dx[ax];
@@ -817,6 +855,11 @@ static int or_check(const or_grid* g, const or_scheme* sc) {
     if (g->system != 0 && g->system != 1) return -2;
     return 0;
 }
+
+/* Error bits of the parallel loops: 1 = a face failed (Roe average),
+ * 2 = a gamma sum was not finite (OR_ENONFINITE). */
+static int or_err_bit(int rc) { return rc == 0 ? 0 : (rc == OR_ENONFINITE ? 2 : 1); }
+static int or_err_code(int err) { return (err & 2) ? OR_ENONFINITE : (err ? -3 : 0); }
 
 /* ------------------------------------------------------------------------ */
 /* Whole-grid entry points (host arrays, same layouts as the C-ABI)          */
@@ -844,8 +887,9 @@ int or_reconstruct_faces(const or_grid* g, int K, int lim, double C_T, double ga
         p[ax] -= 1; /* face j sits between cells j-1 and j */
         double F[5];
         uint8_t fl[10], bd[10];
-        if (or_face_flux(g, &sc, &s, ax, p, F, fl, bd) != 0) {
-            err |= 1;
+        int frc = or_face_flux(g, &sc, &s, ax, p, F, fl, bd);
+        if (frc) {
+            err |= or_err_bit(frc);
             continue;
         }
         for (int f = 0; f < nf; f++) {
@@ -860,7 +904,7 @@ int or_reconstruct_faces(const or_grid* g, int K, int lim, double C_T, double ga
             }
         }
     }
-    return err ? -3 : 0;
+    return or_err_code(err);
 }
 
 /* dU/dt on the whole grid, computed from the face fluxes of each axis. */
@@ -959,11 +1003,10 @@ int or_faces_points(const or_grid* g, int K, int lim, double C_T, double gamma, 
         long idx = face_idx[t];
         int p[3] = {(int)(idx % fn[0]), (int)((idx / fn[0]) % fn[1]), (int)(idx / ((long)fn[0] * fn[1]))};
         p[ax] -= 1;
-        if (or_face_flux(g, &sc, &s, ax, p, out + t * nf, flags ? flags + t * 2 * nf : NULL,
-                         band ? band + t * 2 * nf : NULL) != 0)
-            err |= 1;
+        err |= or_err_bit(or_face_flux(g, &sc, &s, ax, p, out + t * nf, flags ? flags + t * 2 * nf : NULL,
+                                       band ? band + t * 2 * nf : NULL));
     }
-    return err ? -3 : 0;
+    return or_err_code(err);
 }
 
 /* dU/dt at selected cells (flat cell indices). out: [npts][nf]. */
@@ -980,10 +1023,10 @@ int or_dudt_points(const or_grid* g, int K, int lim, double C_T, double gamma, c
         int p[3];
         long bh = 0;
         or_unflatten(g, cell_idx[t], p);
-        if (or_dudt_cell(g, &sc, &s, p, out + t * nf, &bh) != 0) err |= 1;
+        err |= or_err_bit(or_dudt_cell(g, &sc, &s, p, out + t * nf, &bh));
         if (bandhits) bandhits[t] = bh;
     }
-    return err ? -3 : 0;
+    return or_err_code(err);
 }
 
 /* Fill one RK stage on a box of cells around `ctr` with half-width rad
@@ -1005,7 +1048,8 @@ static int or_stage_box(const or_grid* g, const or_scheme* sc, const or_state* s
         for (int d = 0; d < g->ndim; d++)
             if (g->bc[d] == 1) Q[d] = or_bc_index(Q[d], g->n[d], 1);
         double dU[5];
-        if (or_dudt_cell(g, sc, ss, Q, dU, bandhit) != 0) return -1;
+        int rc = or_dudt_cell(g, sc, ss, Q, dU, bandhit);
+        if (rc) return rc;
         for (int f = 0; f < nf; f++) {
             double u0 = or_get(s0, f, Q), us = or_get(ss, f, Q);
             out[(size_t)f * tot + t] = a * u0 + b * (us + dt * dU[f]);
@@ -1045,20 +1089,20 @@ int or_rk3_points(const or_grid* g, int K, int lim, double C_T, double gamma, do
         or_state s0 = {g, U, 0, {0, 0, 0}, {0, 0, 0}};
         or_state s1 = {g, B1, 1, {0, 0, 0}, {0, 0, 0}};
         or_state s2 = {g, B2, 1, {0, 0, 0}, {0, 0, 0}};
-        int ok = or_stage_box(g, &sc, &s0, &s0, ctr, 2 * h, 0.0, 1.0, dt, B1, s1.bn, s1.org, &bh) == 0;
-        ok = ok && or_stage_box(g, &sc, &s0, &s1, ctr, h, 0.75, 0.25, dt, B2, s2.bn, s2.org, &bh) == 0;
-        if (ok) {
+        int src = or_stage_box(g, &sc, &s0, &s0, ctr, 2 * h, 0.0, 1.0, dt, B1, s1.bn, s1.org, &bh);
+        if (src == 0) src = or_stage_box(g, &sc, &s0, &s1, ctr, h, 0.75, 0.25, dt, B2, s2.bn, s2.org, &bh);
+        if (src == 0) {
             double dU[5];
-            ok = or_dudt_cell(g, &sc, &s2, ctr, dU, &bh) == 0;
-            for (int f = 0; ok && f < nf; f++)
+            src = or_dudt_cell(g, &sc, &s2, ctr, dU, &bh);
+            for (int f = 0; src == 0 && f < nf; f++)
                 out[t * nf + f] = (1.0 / 3.0) * or_get(&s0, f, ctr) + (2.0 / 3.0) * (or_get(&s2, f, ctr) + dt * dU[f]);
         }
-        if (!ok) err |= 1;
+        err |= or_err_bit(src);
         if (bandhits) bandhits[t] = bh;
         free(B1);
         free(B2);
     }
-    return err ? -3 : 0;
+    return or_err_code(err);
 }
 
 /* max over cells of sum_d (|u_d| + c) / dx_d (scalar: sum_d |a_d| / dx_d);

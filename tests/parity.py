@@ -65,16 +65,21 @@ def ulp_perturbed(U, seed=97):
     return U * (1.0 + np.ldexp(1.0, -52) * rng.choice([-1.0, 0.0, 1.0], size=U.shape))
 
 
-def conditioning_tol(o, o_pert, scale, rtol=RTOL, factor=4.0, keep=None):
-    """Per-field tolerance for outputs whose FP64 conditioning is worse than
-    rtol: max(rtol * scale, factor * spread), where spread is how far the
-    oracle's own output moves when its input moves by one ulp (measured on
-    the kept samples).  Equals rtol * scale wherever conditioning allows."""
+def one_ulp_spread(o, o_pert, keep=None):
+    """Per field, how far the oracle's own output moves when its input moves
+    by one ulp (on the kept samples): a diagnostic of the conditioning,
+    printed beside the parity error."""
     d = np.abs(np.asarray(o_pert) - np.asarray(o))
     if keep is not None:
         d = d[keep]
-    spread = d.max(axis=0) if d.size else np.zeros(d.shape[-1])
-    return np.maximum(rtol * scale, factor * spread), spread
+    return d.max(axis=0) if d.size else np.zeros(d.shape[-1])
+
+
+def conditioning_tol(o, o_pert, scale, rtol=RTOL, factor=4.0, keep=None):
+    """Per-field tolerance for a multi-step rollout, whose FP64 conditioning
+    is worse than one step's: max(rtol * scale, factor * spread), with the
+    spread of one_ulp_spread.  Per-call and per-step checks use rtol alone."""
+    return np.maximum(rtol * scale, factor * one_ulp_spread(o, o_pert, keep)), one_ulp_spread(o, o_pert, keep)
 
 
 def band_faces(band):

@@ -5,13 +5,13 @@ benchmark times, checked on outputs the oracle computes one by one.
   sampled faces of each axis, sampled cells of dU/dt, and sampled cells of
   one SSP-RK3 step (the oracle evaluates each sample from its dependency
   cone); samples whose cone meets a face in the cutoff band are excluded.
-  The step is held to 1e-12 of each field's largest magnitude.  The
-  per-call face fluxes and divergences along z are worse conditioned: the
-  normal velocity there is only the 1e-2 perturbation, so the mass and
+  Every check is held to 1e-12 of each field's largest magnitude.  The
+  per-call face fluxes and divergences along z are the worst conditioned:
+  the normal velocity there is only the 1e-2 perturbation, so the mass and
   energy fluxes are ~100x smaller than the characteristic terms that
   cancel to form them, and a one-ulp change of the input moves the
-  oracle's own result by ~1e-12 of their maximum.  Those two checks use
-  max(1e-12 * scale, 4 x the oracle's one-ulp spread) per field.
+  oracle's own result by ~1e-12 of their maximum.  That spread is printed
+  beside the error as a diagnostic; it does not widen the bar.
 * 1D Euler N = 4096 seeded Riemann problems, TENO8-M-TVD(minmod),
   C_T = 1e-7: every step of a run compared with the oracle on the same
   input, and the GPU run to t_end against the exact Riemann solution.
@@ -25,7 +25,7 @@ import pytest
 
 import workloads as W
 from oracle import exact_riemann as ER
-from parity import RTOL, conditioning_tol, field_scale, require_gpu, to_dev, to_host, ulp_perturbed
+from parity import RTOL, field_scale, one_ulp_spread, require_gpu, to_dev, to_host, ulp_perturbed
 
 pytestmark = pytest.mark.gpu
 GAMMA = 1.4
@@ -66,11 +66,11 @@ def test_c3_faces_sampled(T, orc, c3):
         assert band.sum() <= 2
         keep = ~band & np.all(flp == flo, axis=1)
         scale = field_scale(Fg)
-        tol, spread = conditioning_tol(Fo, Fp, scale, keep=keep)
+        spread = one_ulp_spread(Fo, Fp, keep=keep)
         err = np.abs(Fg[:, idx].T - Fo)[~band]
         print(f"  max |gpu-oracle| / scale = {(err / scale).max(axis=0)}; "
               f"oracle 1-ulp spread / scale = {spread / scale}", flush=True)
-        assert np.all(err <= tol[None, :]), (err / scale).max(axis=0)
+        assert np.all(err <= RTOL * scale[None, :]), (err / scale).max(axis=0)
         assert np.array_equal(flg[:, idx].T[~band], flo[~band])
         del Fg, flg
 
@@ -84,11 +84,11 @@ def test_c3_divergence_sampled(T, orc, c3):
     keep = bh == 0
     assert keep.sum() >= len(idx) - 5
     scale = field_scale(dg)
-    tol, spread = conditioning_tol(do, dp, scale, keep=keep & (bhp == 0))
+    spread = one_ulp_spread(do, dp, keep=keep & (bhp == 0))
     err = np.abs(dg[:, idx].T - do)[keep]
     print(f"  max |gpu-oracle| / scale = {(err / scale).max(axis=0)}; "
           f"oracle 1-ulp spread / scale = {spread / scale}", flush=True)
-    assert np.all(err <= tol[None, :]), (err / scale).max(axis=0)
+    assert np.all(err <= RTOL * scale[None, :]), (err / scale).max(axis=0)
 
 
 def test_c3_rk3_step_sampled(T, orc, c3):

@@ -187,13 +187,16 @@ def test_flags_do_not_depend_on_the_limiter(T, orc, scheme):
         assert not mism.any(), f"{int(mism.sum())} flag mismatches outside the band"
 
 
-@pytest.mark.parametrize("scale", [1e60, -1e60, 1e-15])
+@pytest.mark.parametrize("scale", [1e60, -1e60, 1e72, -1e72, 1e-15])
 @pytest.mark.parametrize("K", [6, 8])
 def test_scalar_faces_at_extreme_magnitudes(T, orc, scale, K):
     """Scalar data scaled far from O(1): the indicators scale with the data
     squared (about 1e120 at 1e60, where the GPU's paired reciprocals of the
-    indicator denominators, products of two of them, reach about 1e240); the
-    cutoff decisions are scale-invariant while beta stays far above eps.
+    indicator denominators, products of two of them, reach about 1e240).
+    At 1e72 the doubled split values reach about 1e73 and the products about
+    1e296, close to the documented range of the paired reciprocals (each
+    denominator below 2^500, about 3e150).  The cutoff decisions are
+    scale-invariant while beta stays far above eps.
     Faces against the oracle to 1e-12 of the largest magnitude, flags equal
     outside the band."""
     grid = dict(ndim=1, n=[300], dx=[0.05], bc=[0], system=0, adv=[1.0])

@@ -11,27 +11,15 @@
   against the exact measure of known polynomials, the textbook Jiang-Shu
   form on 3-point stencils, and its invariances.
 """
-import os
 from fractions import Fraction as Fr
 
 import numpy as np
 import pytest
 
 from exact_poly import (cell_avg_poly, face_weights, js_beta_of_poly, poly_eval, solve)
+from fixtures import table1
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 STENCILS = {0: (-1, 1), 1: (0, 2), 2: (-2, 0), 3: (0, 3), 4: (-3, 0), 5: (0, 4)}
-
-
-def table1():
-    rows = {}
-    with open(os.path.join(GOLDEN, "table1_candidate_coefficients.txt")) as fh:
-        for line in fh:
-            if not line.strip() or line.startswith("#"):
-                continue
-            parts = line.split()
-            rows[int(parts[0])] = [Fr(p) for p in parts[1:]]
-    return rows
 
 
 def test_table1_rows_are_exact_for_their_polynomial_degree():

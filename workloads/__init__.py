@@ -122,6 +122,10 @@ def square_wave(n: int, lo: float = 0.25, hi: float = 0.5) -> tuple[np.ndarray, 
 # 1D Euler: Riemann problems
 # --------------------------------------------------------------------------
 
+# CFL number of every run (Sec. 4: CFL 0.4 with the SSP Runge-Kutta step;
+# Sec. 3.2.2 chooses the MP alpha so that CFL <= 1/(1 + alpha) holds)
+CFL = 0.4
+
 # (rho, u, p) left and right states of the shock tubes (Sec. 4.2.1)
 SOD = ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
 LAX = ((0.445, 0.698, 3.528), (0.5, 0.0, 0.5710))
