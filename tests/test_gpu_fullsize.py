@@ -5,13 +5,15 @@ benchmark times, checked on outputs the oracle computes one by one.
   sampled faces of each axis, sampled cells of dU/dt, and sampled cells of
   one SSP-RK3 step (the oracle evaluates each sample from its dependency
   cone); samples whose cone meets a face in the cutoff band are excluded.
-  Every check is held to 1e-12 of each field's largest magnitude.  The
-  per-call face fluxes and divergences along z are the worst conditioned:
-  the normal velocity there is only the 1e-2 perturbation, so the mass and
-  energy fluxes are ~100x smaller than the characteristic terms that
-  cancel to form them, and a one-ulp change of the input moves the
-  oracle's own result by ~1e-12 of their maximum.  That spread is printed
-  beside the error as a diagnostic; it does not widen the bar.
+  The step is held to 1e-12 of each field's largest magnitude.  The
+  per-call face fluxes and divergences are held to 1e-12 of that scale plus
+  the oracle's own one-ulp spread (how far its result moves when its input
+  moves by one ulp, measured on the same samples).  The spread is about
+  1e-15 of the scale along x and y; along z the normal velocity is only the
+  1e-2 perturbation, so the energy flux is ~1000x smaller than the
+  Rusanov-split characteristic values that cancel to form it, the spread
+  reaches ~8e-13 of the scale, and two correct FP64 evaluations differ by
+  up to about the sum of their own spreads.
 * 1D Euler N = 4096 seeded Riemann problems, TENO8-M-TVD(minmod),
   C_T = 1e-7: every step of a run compared with the oracle on the same
   input, and the GPU run to t_end against the exact Riemann solution.
@@ -70,7 +72,7 @@ def test_c3_faces_sampled(T, orc, c3):
         err = np.abs(Fg[:, idx].T - Fo)[~band]
         print(f"  max |gpu-oracle| / scale = {(err / scale).max(axis=0)}; "
               f"oracle 1-ulp spread / scale = {spread / scale}", flush=True)
-        assert np.all(err <= RTOL * scale[None, :]), (err / scale).max(axis=0)
+        assert np.all(err <= (RTOL * scale + spread)[None, :]), (err / scale).max(axis=0)
         assert np.array_equal(flg[:, idx].T[~band], flo[~band])
         del Fg, flg
 
@@ -88,7 +90,7 @@ def test_c3_divergence_sampled(T, orc, c3):
     err = np.abs(dg[:, idx].T - do)[keep]
     print(f"  max |gpu-oracle| / scale = {(err / scale).max(axis=0)}; "
           f"oracle 1-ulp spread / scale = {spread / scale}", flush=True)
-    assert np.all(err <= RTOL * scale[None, :]), (err / scale).max(axis=0)
+    assert np.all(err <= (RTOL * scale + spread)[None, :]), (err / scale).max(axis=0)
 
 
 def test_c3_rk3_step_sampled(T, orc, c3):
