@@ -190,6 +190,30 @@ int tenom_rk3_step_cfl(const tenom_grid* grid, int scheme, int limiter, double C
 size_t tenom_workspace_bytes(const tenom_grid* grid, int scheme);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step
+ * of tenom_rk3_step_cfl, same kernels and the same bits, with its scratch
+ * (divergence accumulator, stage states, per-block rate maxima and dt) in a
+ * library-held static device array of TENOM_STATIC_SCRATCH_BYTES instead of
+ * a caller workspace.  The caller still passes U (in/out) and dt_out.
+ *   - Grids whose tenom_workspace_bytes exceeds TENOM_STATIC_SCRATCH_BYTES
+ *     are rejected with TENOM_EWORKSPACE (128 MiB holds a 2D Euler grid of
+ *     1024^2 or a 3D one of 100^3).
+ *   - Each device the call runs on holds its own copy of the array from the
+ *     first call on that device until the process ends; the call looks its
+ *     address up once per device (nothing is allocated by the call itself).
+ *   - Every call on one device shares that device's array, and the array
+ *     keeps the last call's contents; each step writes every part it reads
+ *     first, so nothing needs clearing.  Calls that overlap on one device
+ *     (other streams, other threads) race on the array.
+ * Errors as tenom_rk3_step_cfl.
+ */
+#define TENOM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+size_t tenom_static_scratch_bytes(void);
+int tenom_rk3_step_cfl_noalloc(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma,
+                               double cfl, double* U, double* dt_out, void* stream);
+
+/*
  * Largest signal rate over the cells: max_cells sum_d (|u_d| + c) / dx_d
  * (scalar system: sum_d |a_d| / dx_d).  A step at CFL number sigma is
  * dt = sigma / *out_host.  Synchronises `stream`; a NaN in U yields NaN.

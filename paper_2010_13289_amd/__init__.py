@@ -37,6 +37,7 @@ SYMBOLS = (
     "tenom_batch_autotune", "tenom_batch_times", "tenom_batch_reset_times",
     "tenom_vjp_workspace_bytes", "tenom_flux_divergence_vjp", "tenom_rk3_vjp_workspace_bytes",
     "tenom_rk3_step_vjp", "tenom_rk3_step_stages", "tenom_rk3_step_vjp_stages", "tenom_rk3_step_cfl",
+    "tenom_static_scratch_bytes", "tenom_rk3_step_cfl_noalloc",
 )
 
 
@@ -116,6 +117,8 @@ def lib() -> C.CDLL:
         L.tenom_flux_divergence.argtypes = [gp, C.c_int, C.c_int, dp, dp, vp, vp, vp]
         L.tenom_rk3_step.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, C.c_size_t, vp]
         L.tenom_rk3_step_cfl.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, C.c_size_t, vp, vp]
+        L.tenom_rk3_step_cfl_noalloc.argtypes = [gp, C.c_int, C.c_int, dp, dp, dp, vp, vp, vp]
+        L.tenom_static_scratch_bytes.restype = C.c_size_t
         L.tenom_workspace_bytes.argtypes = [gp, C.c_int]
         L.tenom_workspace_bytes.restype = C.c_size_t
         L.tenom_max_wave_speed.argtypes = [gp, dp, vp, C.POINTER(C.c_double), vp]
@@ -271,6 +274,31 @@ def rk3_step_cfl(U, grid, scheme: int, limiter: int, C_T: float, gamma: float, c
     gc = g.to_c()
     _check(lib().tenom_rk3_step_cfl(C.byref(gc), scheme, limiter, C_T, gamma, cfl, ptr, ws.ptr, ws.nbytes, dptr,
                                     _stream(stream)))
+    return U
+
+
+def static_scratch_bytes() -> int:
+    """Size of the library-held scratch of rk3_step_cfl_noalloc."""
+    return int(lib().tenom_static_scratch_bytes())
+
+
+def rk3_step_cfl_noalloc(U, grid, scheme: int, limiter: int, C_T: float, gamma: float, cfl: float,
+                         stream=None, dt_out=None):
+    """rk3_step_cfl without a workspace: the scratch is the library's static
+    device array (tenom_rk3_step_cfl_noalloc), so the call allocates
+    nothing.  Grids whose workspace_bytes exceed static_scratch_bytes()
+    raise EWORKSPACE.  Overlapping calls on one device race.  Returns U."""
+    g = Grid.of(grid)
+    ptr = _state(U, g)
+    dptr = None
+    if dt_out is not None:
+        import torch
+        if not (dt_out.is_cuda and dt_out.dtype == torch.float64 and dt_out.numel() >= 1 and dt_out.is_contiguous()):
+            raise TenomError(EINVAL, "dt_out must be a contiguous float64 device tensor with at least one element")
+        dptr = C.c_void_p(dt_out.data_ptr())
+    gc = g.to_c()
+    _check(lib().tenom_rk3_step_cfl_noalloc(C.byref(gc), scheme, limiter, C_T, gamma, cfl, ptr, dptr,
+                                            _stream(stream)))
     return U
 
 

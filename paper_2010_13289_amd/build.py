@@ -2,7 +2,7 @@
 
 Steps: regenerate csrc/teno_tables.h from gen_tables.py, compile the eight
 forward and the eight adjoint instantiation units (fields x K), the six
-batched-path units (one per tile shape) and the two C-ABI sources in
+batched-path units (one per tile shape) and the three C-ABI sources in
 parallel with hipcc, link them into paper_2010_13289_amd/libtenom.so.
 
     python -m paper_2010_13289_amd.build [--verbose]
@@ -87,7 +87,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         objs.append(obj)
         cmds.append([hipcc, *HIPCC_FLAGS, f"-DTENOM_TILE={t}", "-c",
                      os.path.join(CSRC, "tenom_batch_inst.hip"), "-o", obj])
-    for src in ("tenom_abi.hip", "tenom_batch.hip"):
+    for src in ("tenom_abi.hip", "tenom_batch.hip", "tenom_noalloc.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         objs.append(obj)
         cmds.append([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])

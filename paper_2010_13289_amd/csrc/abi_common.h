@@ -31,6 +31,12 @@ inline int hip_fail(hipError_t e, const char* what) {
   return fail(TENOM_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// One SSP-RK3 step with dt from the CFL condition on the device, on the
+// workspace ws of ws_bytes bytes (tenom_rk3_step_cfl; defined in
+// tenom_abi.hip).
+int rk3_step_cfl_ws(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double cfl, double* U,
+                    void* ws, size_t ws_bytes, double* dt_out, hipStream_t s);
+
 // scheme -> K (0 if invalid) and the adaptive-cutoff flag
 inline int scheme_K(int scheme, bool* adaptive) {
   const int K = scheme & 0xff;

@@ -612,11 +612,21 @@ int tenom_rk3_step(const tenom_grid* grid, int scheme, int limiter, double C_T, 
 int tenom_rk3_step_cfl(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double cfl,
                        double* U, void* ws, size_t ws_bytes, double* dt_out, void* stream) {
   g_err[0] = 0;
+  return tenom::abi::rk3_step_cfl_ws(grid, scheme, limiter, C_T, gamma, cfl, U, ws, ws_bytes, dt_out,
+                                     (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// The step of tenom_rk3_step_cfl on the workspace `ws` (checks included);
+// also the body of the entry point whose workspace is the library's static
+// scratch array.
+int tenom::abi::rk3_step_cfl_ws(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double cfl,
+                                double* U, void* ws, size_t ws_bytes, double* dt_out, hipStream_t s) {
   if (!(cfl > 0.0) || !isfinite(cfl)) return fail(TENOM_EINVAL, "cfl must be finite and > 0 (got %g)", cfl);
   // dt is formed on the device; 1.0 stands in for it in the host checks
   const int rc = rk3_step_checks(grid, scheme, limiter, C_T, gamma, 1.0, U, ws, ws_bytes);
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
   const size_t state = state_bytes(grid);
   double* R = (double*)ws;
   double* U1 = (double*)((char*)ws + state);
@@ -631,6 +641,8 @@ int tenom_rk3_step_cfl(const tenom_grid* grid, int scheme, int limiter, double C
   if (e != hipSuccess) return hip_fail(e, "step-size kernel launch");
   return rk3_stages(grid, scheme, limiter, C_T, gamma, 0.0, U, R, U1, U2, s, dt_dev);
 }
+
+extern "C" {
 
 int tenom_rk3_step_stages(const tenom_grid* grid, int scheme, int limiter, double C_T, double gamma, double dt,
                           double* U, double* U1, double* U2, void* ws, size_t ws_bytes, void* stream) {

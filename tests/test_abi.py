@@ -131,6 +131,18 @@ def test_cfl_step_errors(lib):
     assert step(C.byref(g), 6, 9, 1e-5, 1.4, 0.4, DUMMY, ws, need, None, None) == T.EUNSUPPORTED
 
 
+def test_noalloc_step_rejects_oversized_grids_before_touching_the_device(lib):
+    """The allocation-free step checks the grid's scratch need against its
+    static array first: a 128^3 Euler grid needs 3 states (252 MB) and is
+    refused without any HIP call."""
+    assert lib.tenom_static_scratch_bytes() == 128 << 20
+    g = grid(n=[128, 128, 128])
+    assert lib.tenom_workspace_bytes(C.byref(g), 6) > lib.tenom_static_scratch_bytes()
+    rc = lib.tenom_rk3_step_cfl_noalloc(C.byref(g), 6, 1, 1e-5, 1.4, 0.4, DUMMY, None, None)
+    assert rc == T.EWORKSPACE
+    assert b"static scratch" in lib.tenom_last_error()
+
+
 def test_scheme_and_limiter_ids(lib):
     g = grid()
     bad = C.c_void_p(0x2000)
