@@ -46,6 +46,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402  (seeded inputs; no scheme arithmetic)
+from paper_2010_13289_amd import opcount as O  # noqa: E402  (itemised operation counts)
 
 METRIC = "face-reconstructions/s + % HBM roofline (fwd, fwd+adjoint, batched vs plain)"
 N = 256
@@ -58,21 +59,13 @@ CFL = W.CFL
 PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 FP64 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 operations per Euler face vector (3D, K = 6, MP limiter),
-# FMA counted as 2, every other arithmetic, min/max or compare as 1, a
-# division or square root as 1.  Breakdown (per face vector):
-#   cell primitives and physical flux, once per cell     22
-#   Rusanov alpha (max over 6 cells)                       5
-#   Roe average and eigenvector constants                 38
-#   projection of 6 U and 6 F vectors on L               264
-#   Rusanov split of 5 fields x 6 cells                  150
-#   TENO-M, 10 scalar reconstructions x 193            1930
-#   back-projection with R                                20
-#   divergence and stage update, once per cell            20
-FLOPS_PER_FACE_VECTOR = 2449
+# Algorithmic FP64 operations per face vector, itemised in
+# paper_2010_13289_amd/opcount.py (FMA = 2, every other arithmetic, min/max,
+# compare, division or square root = 1) and pinned by tests/test_opcount.py.
+FLOPS_PER_FACE_VECTOR = O.face_vector_ops("euler", 3, SCHEME, O.LIM_MP)
 # Algorithmic HBM bytes per cell and step: U^(s) read and U^(s+1) written in
 # every stage, U^n also read in stages 2 and 3 (5 fields x 8 bytes each).
-BYTES_PER_CELL_STEP = 320
+BYTES_PER_CELL_STEP = O.rk3_bytes_per_cell(5)
 
 # HBM bytes per launch of each sweep kind at 256^3, averaged over the three
 # stages, from two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE scaled
@@ -84,6 +77,9 @@ MEASURED_TRAFFIC = {"sweep_x": 1.3425e9, "sweep_y": 2.0766e9, "sweep_z": 2.5240e
 # batched sweep, 4096 problems, averaged over the stages, per tile shape
 # (64x1, 128x1, 128x2, 256x1, 256x2, 512x1): smaller tiles re-read more halo
 MEASURED_TRAFFIC_BATCH = (1.2748e9, 1.1482e9, 1.0861e9, 1.0858e9, 1.0548e9, 1.0545e9)
+TRAFFIC_NOTE = ("recorded, not measured in this run: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this benchmark "
+                "on the kernel sources whose digest is TRAFFIC_SOURCE_DIGEST (null for any other build); "
+                "see the profiles directory")
 
 
 # sources of the adjoint only: the forward and batched sweeps whose traffic
@@ -126,16 +122,9 @@ def parse():
 
 
 # Algorithmic FP64 operations per 1D Euler face vector, K = 8, MP limiter
-# (same counting rules as FLOPS_PER_FACE_VECTOR):
-#   cell primitives, flux and Roe inputs, once per cell     30
-#   Rusanov alpha (max over 8 cells)                         8
-#   Roe average and eigenvector constants                   23
-#   projection of 8 U and 8 F vectors on L                 240
-#   Rusanov split of 3 fields x 8 cells                     72
-#   TENO-M, 6 scalar reconstructions x 297               1782
-#   back-projection with R                                  20
-#   divergence and stage update, once per cell              18
-FLOPS_PER_FACE_VECTOR_1D_K8 = 2193
+# (the batched sweep), and per 2D face vector of the adjoint's VJP, K = 6, MP.
+FLOPS_PER_FACE_VECTOR_1D_K8 = O.face_vector_ops("euler", 1, 8, O.LIM_MP)
+FLOPS_PER_VJP_FACE_VECTOR_2D_K6 = O.adjoint_face_vector_ops(2, 6, O.LIM_MP)
 
 
 def run_adjoint(args):
@@ -145,9 +134,15 @@ def run_adjoint(args):
     at rest at uniform pressure, so its acoustic characteristic fields carry
     only rounding-level signals whose cutoff decisions are set by rounding:
     the loss is not differentiable at any scale differences can resolve.
-    The difference check therefore runs the same grid, state, steps and
-    checkpointing with C_T = 0 (every candidate smooth, no decision), where
-    the rollout is smooth; the MP gradient's size is reported beside it."""
+    Two difference checks stand beside the timing:
+      * the same grid, state, steps and checkpointing with C_T = 0 (every
+        candidate smooth, no decision), where the rollout is smooth;
+      * the scheme as configured (C_T = 1e-5, MP) on the same grid with the
+        state set in motion (small seeded velocity and pressure
+        perturbations), over 24 steps with a checkpoint every 20: a
+        direction counts where the perturbed rollouts take every smoothness
+        decision of the unperturbed one and the differences at two step
+        sizes agree."""
     import numpy as np
     import torch
 
@@ -214,8 +209,11 @@ def run_adjoint(args):
             ad = float((g0 * V).sum().item())
             rows.append({"fd_h1e-5": fd[0], "fd_h1e-6": fd[1], "adjoint": ad,
                          "rel_err": abs(fd[1] - ad) / max(abs(ad), 1e-300)})
+    cutoff_check = fd_check_cutoff(T, n, args.fd_directions)
     vjp_n, vjp_ms = prof["vjp_axis"]
     faces = 2 * n * n
+    vjp_avg_s = vjp_ms / 1e3 / max(vjp_n, 1)
+    vjp_flops = FLOPS_PER_VJP_FACE_VECTOR_2D_K6 * n * n  # one axis: n^2 periodic faces
     return {
         "metric": METRIC,
         "value": 3 * steps * faces / t_bwd,
@@ -240,13 +238,77 @@ def run_adjoint(args):
         "forward_with_checkpoints_s": t_fwd_ck,
         "backward_s": t_bwd,
         "backward_over_forward": t_bwd / t_fwd,
-        "vjp_axis_avg_ms": vjp_ms / max(vjp_n, 1),
+        "vjp_axis_avg_ms": vjp_avg_s * 1e3,
         "vjp_axis_launches": vjp_n,
+        "roofline": {"bound": "alu", "kernel": "vjp_axis", "achieved": vjp_flops / vjp_avg_s / 1e12,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": vjp_flops / vjp_avg_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
+                     "avg_launch_ms": vjp_avg_s * 1e3, "flops_per_launch": vjp_flops},
         "loss": L_mp,
         "mp_gradient_max_per_field": g_mp.abs().amax(dim=(1, 2)).cpu().tolist(),
         "fd_check_ct0": {"directions": len(rows), "loss": L0,
                          "max_rel_err": max(r["rel_err"] for r in rows) if rows else None, "rows": rows},
+        "fd_check_cutoff": cutoff_check,
     }
+
+
+def fd_check_cutoff(T, n, want, steps=24, ck=20, max_tries=32, h=1e-8):
+    """Central differences of the TENO6-M-MP (C_T = 1e-5) rollout gradient on
+    the moving 2D state along smooth local directions (random-phase fields
+    under a Gaussian window of width 1/64).  Every direction tried is
+    reported; a direction is "strict" where the rollouts from U +- hV take
+    every smoothness decision of the unperturbed one and the differences at
+    h and h/2 agree to 1e-6 (rounding in the differences resolves 1e-6).  The difference is taken on the final states:
+    L(U+) - L(U-) = sum (rho+ - rho-)(rho+ + rho- - 2 rho_T) dx^2 / 2."""
+    import numpy as np
+    import torch
+    ct = 1e-5
+    U0h, dx = W.moving_density_modes_2d(n, seed=5)
+    Th, _ = W.moving_density_modes_2d(n, seed=6)
+    grid = dict(ndim=2, n=[n, n], dx=[dx, dx], bc=[0, 0], system=1)
+    U0 = torch.from_numpy(U0h).to("cuda")
+    dt = CFL / T.max_wave_speed(U0, grid, GAMMA)
+
+    def final_rho(V):
+        return T.rollout(V, grid, 6, T.LIM_MP, ct, GAMMA, dt, steps, checkpoint=steps)[0]
+
+    target = final_rho(torch.from_numpy(Th).to("cuda")).detach().clone()
+    U = U0.clone().requires_grad_(True)
+    Uf = T.rollout(U, grid, 6, T.LIM_MP, ct, GAMMA, dt, steps, checkpoint=ck)
+    (0.5 * ((Uf[0] - target) ** 2).sum() * dx * dx).backward()
+    g = U.grad.detach()
+
+    def central(V, hh):
+        with torch.no_grad():
+            rp, rm = final_rho(U0 + hh * V), final_rho(U0 - hh * V)
+            return float((0.5 * (rp - rm) * (rp + rm - 2.0 * target)).sum().item()) * dx * dx / (2.0 * hh)
+
+    ref = T.rollout_flags(U0, grid, 6, T.LIM_MP, ct, GAMMA, dt, steps)
+    scale = torch.from_numpy(np.abs(U0h).max(axis=(1, 2), keepdims=True)).to("cuda")
+    rows, strict = [], 0
+    for d in range(max_tries):
+        if strict >= want:
+            break
+        V = torch.from_numpy(W.local_direction_2d(U0h.shape, seed=d, width=1.0 / 64.0)).to("cuda") * scale
+        same = (T.rollout_flags(U0 + h * V, grid, 6, T.LIM_MP, ct, GAMMA, dt, steps, ref=ref)
+                and T.rollout_flags(U0 - h * V, grid, 6, T.LIM_MP, ct, GAMMA, dt, steps, ref=ref))
+        fd, fd2 = central(V, h), central(V, h / 2)
+        ad = float((g * V).sum().item())
+        ok = same and abs(fd - fd2) <= 1e-6 * abs(fd)
+        strict += ok
+        rows.append({"fd": fd, "fd_half_h": fd2, "adjoint": ad, "same_decisions": bool(same), "strict": bool(ok),
+                     "rel_err": abs(fd - ad) / max(abs(ad), 1e-300)})
+    del ref
+    errs = [r["rel_err"] for r in rows]
+    serrs = [r["rel_err"] for r in rows if r["strict"]]
+    return {"scheme": "TENO6-M-MP", "C_T": ct, "steps": steps, "checkpoint": ck, "h": h,
+            "state": f"{n}^2 moving density modes (W.moving_density_modes_2d, seed 5; target seed 6)",
+            "directions": "W.local_direction_2d(seed=d, width=1/64) times each field's max |U|",
+            "directions_tried": len(rows), "directions_strict": strict,
+            "max_rel_err_strict": max(serrs) if serrs else None,
+            "directions_within_1e-6": sum(e <= 1e-6 for e in errs),
+            "max_rel_err_all": max(errs) if errs else None, "median_rel_err_all": float(np.median(errs)),
+            "gradient_max_per_field": g.abs().amax(dim=(1, 2)).cpu().tolist(), "rows": rows}
 
 
 def run_batched(args):
@@ -322,6 +384,7 @@ def run_batched(args):
             "steps_timed": pp,
             "face_reconstructions_per_s": 3 * faces_per_stage / pp_wall,
             "batched_speedup": pp_wall / sec_per_step,
+            "graph": per_problem_graph(plan, U, U0, scheme, lim, ct, pp, sec_per_step, faces_per_stage),
         }
     value = faces / (graph_ms / 1e3)
     out = {
@@ -357,6 +420,7 @@ def run_batched(args):
             "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": (MEASURED_TRAFFIC_BATCH[best] if kernel_source_digest() == TRAFFIC_SOURCE_DIGEST
                         else None),
+            "traffic_source": TRAFFIC_NOTE,
             "avg_launch_ms": avg_s * 1e3,
             "flops_per_launch": FLOPS_PER_FACE_VECTOR_1D_K8 * faces_per_stage,
         },
@@ -367,6 +431,39 @@ def run_batched(args):
     }
     plan.close()
     return out
+
+
+def per_problem_graph(plan, U, U0, scheme, lim, ct, reps, sec_per_step, faces_per_stage):
+    """One step of the per-problem launches (4 kernels for each problem)
+    captured in one HIP graph and replayed `reps` times: the per-problem
+    kernels' own cost without host launch overhead."""
+    import torch
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up off the capture, as torch asks
+        plan.rk3(U, scheme, lim, ct, GAMMA, CFL, steps=1, first=0, count=1)
+    torch.cuda.current_stream().wait_stream(side)
+    U.copy_(U0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        for p in range(plan.count):
+            plan.rk3(U, scheme, lim, ct, GAMMA, CFL, steps=1, first=p, count=1)
+    graph.replay()  # untimed
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del graph
+    return {"nodes_per_step": 4 * plan.count, "ms_per_step": ms,
+            "face_reconstructions_per_s": 3 * faces_per_stage / (ms / 1e3),
+            "batched_speedup": ms / 1e3 / sec_per_step}
 
 
 # (name, scheme, limiter, C_T) of the variant report; classic TENO first in
@@ -408,14 +505,21 @@ def run_variants(T, U0, grid, n, steps, warmup):
         ms = (t1 - t0) / steps * 1e3
         group = name.split("-")[0]
         ref.setdefault(group, ms)
+        sweep_ms = {k: prof[k][1] / max(prof[k][0], 1) for k in ("sweep_x", "sweep_y", "sweep_z")}
+        kind = max(sweep_ms, key=sweep_ms.get)  # the slowest sweep of the variant
+        flops_launch = O.face_vector_ops("euler", 3, scheme & 0xFF, lim, bool(scheme & 0x100)) * n ** 3
+        achieved = flops_launch / (sweep_ms[kind] / 1e3) / 1e12
         rows.append({
             "variant": name, "scheme": scheme, "limiter": lim, "C_T": ct, "ms_per_step": ms,
             "face_vectors_per_s": 9 * n ** 3 / (ms / 1e3),
             "ratio_vs_classic": ms / ref[group],
-            "sweep_avg_ms": {k: prof[k][1] / max(prof[k][0], 1) for k in ("sweep_x", "sweep_y", "sweep_z")},
+            "sweep_avg_ms": sweep_ms,
+            "roofline": {"bound": "alu", "kernel": kind, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "flops_per_launch": flops_launch},
             "state_finite": T.check_finite(U, grid),
         })
-        print(f"# {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        print(f"# {name}: {ms:.3f} ms/step, {kind} {sweep_ms[kind]:.3f} ms, frac {achieved / PEAK_FP64_TFLOPS:.3f}",
+              file=sys.stderr, flush=True)
         del ws, U
     return rows
 
@@ -578,6 +682,7 @@ def main():
             "frac": achieved / PEAK_FP64_TFLOPS,
             "traffic": (MEASURED_TRAFFIC.get(kind) if n == N and kernel_source_digest() == TRAFFIC_SOURCE_DIGEST
                         else None),
+            "traffic_source": TRAFFIC_NOTE,
             "avg_launch_ms": avg_s * 1e3,
             "flops_per_launch": flops_launch,
         },

@@ -554,6 +554,33 @@ class Rk3Rollout:
         return _Fn.apply(U0)
 
 
+def rollout_flags(U0, grid, scheme: int, limiter: int, C_T: float, gamma: float, dt: float, steps: int,
+                  ref=None):
+    """Smoothness flags of every stage and axis of a `steps`-step fixed-dt
+    rollout from U0 (U0 is left untouched): a list of [2, nf, faces...]
+    uint8 tensors in the order step, stage, axis.  With ref (the list of a
+    previous call) it returns instead whether every flag equals ref's, e.g.
+    to tell whether a perturbed rollout takes the same decisions."""
+    import torch
+    g = Grid.of(grid)
+    U = U0.detach().clone().contiguous()
+    U1, U2 = torch.empty_like(U), torch.empty_like(U)
+    ws = Workspace(g, scheme, U.device)
+    out, k = [], 0
+    for _ in range(steps):
+        stage_in = U.clone()
+        rk3_step(U, g, scheme, limiter, C_T, gamma, dt, workspace=ws, stages=(U1, U2))
+        for S in (stage_in, U1, U2):
+            for axis in range(g.ndim):
+                _, fl = reconstruct_faces(S, g, scheme, limiter, C_T, gamma, axis, return_flags=True)
+                if ref is None:
+                    out.append(fl)
+                elif not torch.equal(fl, ref[k]):
+                    return False
+                k += 1
+    return out if ref is None else True
+
+
 def rollout(U0, grid, scheme: int, limiter: int, C_T: float, gamma: float, dt: float, steps: int,
             checkpoint: int = 20):
     """Differentiable `steps`-step rollout (see Rk3Rollout)."""

@@ -202,3 +202,59 @@ def test_rollout_gradient_matches_differences(T):
             print(f"[rollout grad] direction {d}: fd {fd} adjoint {ad}", flush=True)
             assert abs(fd[0] - fd[1]) <= 1e-6 * abs(fd[1])
             assert abs(fd[1] - ad) <= 1e-7 * abs(ad), (d, fd, ad)
+
+
+def test_rollout_gradient_with_the_cutoff_on(T):
+    """TENO6-M-MP with C_T = 1e-5 over 24 fixed steps (checkpoint 20, so
+    two replayed segments) on a moving 2D state: 64 density modes (|k| <= 8)
+    and a jump on a circle, set in motion by small velocity and pressure
+    perturbations (|k| <= 4) so that every characteristic field carries a
+    signal.  Directions are smooth and local (random-phase fields under a
+    Gaussian window), so that a step along them moves the smoothness
+    indicators by about the state's own relative amount.  A direction
+    counts where the rollouts from U +- hV (h = 1e-8) take every smoothness
+    decision of every stage as the rollout from U, and the differences at
+    h and h/2 agree to 1e-6 (no limiter kink crossed, and rounding in the
+    differences resolves 1e-6 along that direction); at least 8 must count,
+    and on each the frozen-decision gradient equals the central difference
+    at h to 1e-6.  The difference is taken on the final states,
+    L(U+) - L(U-) = sum (rho+ - rho-)(rho+ + rho- - 2 rho_T) / 2."""
+    import torch
+    n, steps, ck, C_T = 128, 24, 20, 1e-5
+    grid = dict(ndim=2, n=[n, n], dx=[1.0 / n] * 2, bc=[0, 0], system=1)
+    U0h, _ = W.moving_density_modes_2d(n, seed=5, kmax=4.0, density_kmax=8)
+    Th, _ = W.moving_density_modes_2d(n, seed=6, kmax=4.0, density_kmax=8)
+    U0 = to_dev(U0h)
+    dt = 0.4 / T.max_wave_speed(U0, grid, GAMMA)
+    target = T.rollout(to_dev(Th), grid, 6, T.LIM_MP, C_T, GAMMA, dt, steps, checkpoint=steps).detach()[0].clone()
+    U = U0.clone().requires_grad_(True)
+    _rollout_loss(T, grid, 6, T.LIM_MP, C_T, dt, steps, target)(U, ck).backward()
+    g = U.grad.detach()
+    assert bool(torch.isfinite(g).all()) and float(g.abs().max()) > 0
+
+    def final_rho(V):
+        return T.rollout(V, grid, 6, T.LIM_MP, C_T, GAMMA, dt, steps, checkpoint=steps)[0]
+
+    def central(V, h):
+        with torch.no_grad():
+            rp, rm = final_rho(U0 + h * V), final_rho(U0 - h * V)
+            return float((0.5 * (rp - rm) * (rp + rm - 2.0 * target)).sum().item()) / (2.0 * h)
+
+    ref = T.rollout_flags(U0, grid, 6, T.LIM_MP, C_T, GAMMA, dt, steps)
+    scale = torch.from_numpy(np.abs(U0h).max(axis=(1, 2), keepdims=True)).to(U0.device)
+    h = 1e-8
+    usable, tried = 0, 0
+    while usable < 8 and tried < 32:
+        V = to_dev(W.local_direction_2d(U0h.shape, seed=tried)) * scale
+        tried += 1
+        same = (T.rollout_flags(U0 + h * V, grid, 6, T.LIM_MP, C_T, GAMMA, dt, steps, ref=ref)
+                and T.rollout_flags(U0 - h * V, grid, 6, T.LIM_MP, C_T, GAMMA, dt, steps, ref=ref))
+        fd, fd2 = central(V, h), central(V, h / 2)
+        ad = float((g * V).sum().item())
+        print(f"[rollout grad C_T=1e-5] direction {tried}: same decisions {same}, fd {fd:.12e} "
+              f"(h/2: {fd2:.12e}), adjoint {ad:.12e}", flush=True)
+        if not same or abs(fd - fd2) > 1e-6 * abs(fd):
+            continue
+        usable += 1
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (tried, fd, ad)
+    assert usable >= 8, f"only {usable} of {tried} directions kept every decision"

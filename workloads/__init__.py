@@ -314,3 +314,59 @@ def density_modes_2d(n: int = 1024, seed: int = 5, modes: int = 64, kmax: int = 
     rho = np.where((x - 0.5) ** 2 + (y - 0.5) ** 2 < radius * radius, 0.5 * rho, rho)
     zero = np.zeros_like(rho)
     return conservative(rho, [zero, zero], 1.0, gamma), 1.0 / n
+
+
+def smooth_direction_2d(shape, seed: int, kmax: float = 8.0) -> np.ndarray:
+    """A random direction for difference checks on an [nf][n][n] state: per
+    field a seeded random-phase field with modes 1 <= |k| <= kmax and max
+    magnitude 1 (smooth, so that a small step along it changes the
+    smoothness indicators by about the same relative amount as the state)."""
+    nf, n = shape[0], shape[1]
+    return np.stack([_random_phase_field_2d(n, min(kmax, n / 4.0), 7919 * seed + f, 1.0) for f in range(nf)])
+
+
+def local_direction_2d(shape, seed: int, width: float = 1.0 / 16.0, kmax: float = 8.0) -> np.ndarray:
+    """smooth_direction_2d(shape, seed) times a Gaussian window of the given
+    width (a fraction of the periodic unit square) centred at a seeded
+    random point: a smooth direction whose influence stays local."""
+    n = shape[1]
+    rng = np.random.default_rng(104729 + seed)
+    cx, cy = rng.uniform(0.0, 1.0, size=2)
+    x1 = cell_centres(n, 0.0, 1.0)
+    dx_ = np.abs(x1 - cx)
+    dy_ = np.abs(x1 - cy)
+    dx_ = np.minimum(dx_, 1.0 - dx_)  # periodic distance
+    dy_ = np.minimum(dy_, 1.0 - dy_)
+    win = np.exp(-(dy_[:, None] ** 2 + dx_[None, :] ** 2) / (2.0 * width * width))
+    return smooth_direction_2d(shape, seed, kmax) * win[None]
+
+
+def _random_phase_field_2d(n: int, kmax: float, seed: int, amp: float) -> np.ndarray:
+    """Real periodic field on an n^2 grid: unit-magnitude modes with uniform
+    random phase for integer wavevectors 1 <= |k|_2 <= kmax, scaled so that
+    max|field| = amp.  Array order [y][x]."""
+    rng = np.random.default_rng(seed)
+    ky = np.fft.fftfreq(n, d=1.0 / n)[:, None]
+    kx = np.fft.rfftfreq(n, d=1.0 / n)[None, :]
+    kk = np.sqrt(kx * kx + ky * ky)
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=kk.shape)
+    spec = np.where((kk >= 1.0) & (kk <= kmax), np.exp(1j * phase), 0.0)
+    f = np.fft.irfftn(spec, s=(n, n), axes=(0, 1))
+    return f * (amp / np.max(np.abs(f)))
+
+
+def moving_density_modes_2d(n: int = 1024, seed: int = 5, amp: float = 1e-2, kmax: float = 16.0,
+                            density_kmax: int = 32, gamma: float = 1.4) -> tuple[np.ndarray, float]:
+    """density_modes_2d(n, seed, kmax=density_kmax) set in motion: seeded
+    random-phase velocity perturbations (max |u|, |v| = amp) and a pressure
+    1 + a perturbation of max amp, modes 1 <= |k| <= kmax (capped at n/4),
+    seeds 1000 seed + 1..3.  Every characteristic field then carries a
+    signal far above rounding.  Returns (U[4][n][n], dx)."""
+    U, dx = density_modes_2d(n, seed=seed, kmax=density_kmax, gamma=gamma)
+    rho = U[0]
+    km = min(kmax, n / 4.0)
+    u = _random_phase_field_2d(n, km, 1000 * seed + 1, amp)
+    v = _random_phase_field_2d(n, km, 1000 * seed + 2, amp)
+    p = 1.0 + _random_phase_field_2d(n, km, 1000 * seed + 3, amp)
+    return conservative(rho, [u, v], p, gamma), dx
+
