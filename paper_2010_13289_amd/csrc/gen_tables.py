@@ -10,16 +10,22 @@ reconstruction is exactly translation-equivariant.
 * the smoothness measures beta_{k,r} of the candidates and beta_K of the
   full stencil (Sec. 2.2): sum_{j=1}^{r-1} int_{-1/2}^{1/2} (p^(j))^2 dxi of
   the degree r-1 polynomial whose cell averages are the stencil values,
-  emitted as sum_q w_q y_q^2 with y = L^T D from an exact LDL^T factorisation,
+  emitted as a positive sum of squares sum_q w_q y_q^2: six points from an
+  exact LDL^T factorisation in the differences (y = L^T D); eight points
+  from the exact LDL^T over the polynomial's Taylor coefficients, each row
+  written in the differences with coprime integer coefficients and the
+  weights times one common scale (beta_scale), so that almost every
+  constant is an instruction literal (see emit),
 * the optimal (maximum-order) linear weights d_k (Sec. 3.3).
 
 Run: python gen_tables.py > teno_tables.h  (the build does this).
 """
 from __future__ import annotations
 
+import struct
 import sys
 from fractions import Fraction as Fr
-from math import factorial
+from math import factorial, gcd
 
 # candidate stencils S_k as offsets [lo, hi] relative to cell i (Table 1)
 CANDIDATES = [(-1, 1), (0, 2), (-2, 0), (0, 3), (-3, 0), (0, 4)]
@@ -128,6 +134,59 @@ def optimal_weights(K):
     return d
 
 
+def taylor_rows(lo, hi):
+    """beta on the stencil [lo, hi] as sum_q w_q (row_q . D)^2 with integer
+    rows: the exact LDL^T of the measure's Gram matrix over the Taylor
+    coefficients a_1 .. a_{r-1} of the polynomial about x_i (ascending),
+    each row of L^T a written in the differences D and scaled to coprime
+    integers (the scale moves into w_q).  Returns [(ints, w)]."""
+    r = hi - lo + 1
+    n = r - 1
+    P = poly_map(lo, hi)
+    T = values_from_diffs(r)
+    # Taylor coefficients a_l (l = 1..r-1) in the differences
+    M = [[sum(P[l][a] * T[a][j] for a in range(r)) for j in range(n)] for l in range(1, r)]
+
+    def mom(e):
+        return Fr(0) if e % 2 else 2 * Fr(1, 2) ** (e + 1) / (e + 1)
+
+    H = [[Fr(0)] * n for _ in range(n)]
+    for j in range(1, r):
+        for k1 in range(j, r):
+            for k2 in range(j, r):
+                H[k1 - 1][k2 - 1] += (Fr(factorial(k1), factorial(k1 - j)) * Fr(factorial(k2), factorial(k2 - j))
+                                      * mom(k1 + k2 - 2 * j))
+    L, w = ldl(H)
+    rows = []
+    for q in range(n):
+        row = [sum(L[i][q] * M[i][j] for i in range(n)) for j in range(n)]
+        den = 1
+        for c in row:
+            den = den * c.denominator // gcd(den, c.denominator)
+        ints = [c * den for c in row]
+        g = 0
+        for c in ints:
+            g = gcd(g, abs(int(c)))
+        ints = [c / g for c in ints]
+        scale = Fr(den, g)
+        rows.append((ints, w[q] / (scale * scale)))
+    # the form is the measure: sum_q w_q (row_q . D)^2 == D^T Q D
+    Q = diff_quadratic(lo, hi)
+    for i in range(n):
+        for j in range(n):
+            assert sum(wq * ints[i] * ints[j] for ints, wq in rows) == Q[i][j]
+    return rows
+
+
+def literal_ok(x: Fr) -> bool:
+    """True when x is a double whose low 32 bits are zero: such a constant
+    is a 32-bit literal of the instruction, with no register to load."""
+    if x != Fr(float(x)):
+        return False
+    bits = struct.unpack("<Q", struct.pack("<d", float(x)))[0]
+    return (bits & 0xFFFFFFFF) == 0
+
+
 def lit(x: Fr) -> str:
     """A double literal for the exact rational x: p/q evaluated at compile
     time when p and q are exact doubles (IEEE division rounds correctly),
@@ -158,9 +217,33 @@ def linear_form(coefs, names):
     return expr
 
 
-def emit(K: int) -> str:
-    nk = K - 2
+def candidate_coeffs(K: int, k: int) -> list:
+    """f_k - v_i = sum_j coefs[j] D[j] (Table 1 candidate k, differences)."""
     c0 = K // 2 - 1  # index of v_i in the K stencil values
+    a, b = CANDIDATES[k]
+    fc = face_coeffs(a, b)
+    coefs = [Fr(0)] * (K - 1)
+    for jj, m in enumerate(range(a, b + 1)):
+        idx = m + c0  # stencil index of offset m
+        if idx > c0:
+            for j in range(c0, idx):
+                coefs[j] += fc[jj]
+        elif idx < c0:
+            for j in range(idx, c0):
+                coefs[j] -= fc[jj]
+    return coefs
+
+
+def emit(K: int, literal: bool) -> str:
+    """Device code of one scheme.  literal: every constant that multiplies
+    data is, where the exact rationals allow, a double whose low 32 bits are
+    zero (an instruction literal): candidates as 1/den times an integer
+    form, the indicators in integer Taylor-coefficient rows with weights
+    scaled by one common factor (beta_scale, a power of two times the lcm
+    of the candidate stencils' weight denominators).  Otherwise the rational
+    coefficients are used directly (a triangular LDL^T in the differences)
+    and beta_scale = 1."""
+    nk = K - 2
     lo_full = -(K // 2) + 1
     lines = []
     w = lines.append
@@ -176,55 +259,77 @@ def emit(K: int) -> str:
         expr = f"k == {k} ? {lit(d[k])} : {expr}"
     w(f"    return {expr};")
     w("  }")
+    names = [f"D[{j}]" for j in range(K - 1)]
+    cand = [candidate_coeffs(K, k) for k in range(nk)]
+    stencils = [(k, CANDIDATES[k]) for k in range(nk)] + [("K", (lo_full, K // 2))]
+    scale = Fr(1)
+    if literal:
+        trows = {tag: taylor_rows(a, b) for tag, (a, b) in stencils}
+        den = 1
+        for tag, _ in stencils:
+            if tag == "K":
+                continue
+            for _, wq in trows[tag]:
+                den = den * wq.denominator // gcd(den, wq.denominator)
+        scale = Fr(den)
+        while scale > 2:
+            scale /= 2
+        for tag, _ in stencils:
+            if tag != "K":
+                assert all(literal_ok(wq * scale) for _, wq in trows[tag]), tag
+    w("  // every beta below is beta_scale times the measure of Eq. measureTENO;")
+    w("  // the cutoff scales eps by the same factor")
+    w(f"  static constexpr double beta_scale = {lit(scale)};")
     # candidates relative to v_i
     w("  // candidate fluxes minus v_i, from the candidate stencils of Table 1")
     w("  static __device__ __forceinline__ void candidates(const double* D, double* c) {")
-    names = [f"D[{j}]" for j in range(K - 1)]
-    cand_coefs = []
+    cand_den = []
     for k in range(nk):
-        a, b = CANDIDATES[k]
-        fc = face_coeffs(a, b)
-        # f_k - v_i = sum_m c_m (v_m - v_i), v_m - v_i in differences
-        coefs = [Fr(0)] * (K - 1)
-        for jj, m in enumerate(range(a, b + 1)):
-            idx = m + c0  # stencil index of offset m
-            if idx > c0:
-                for j in range(c0, idx):
-                    coefs[j] += fc[jj]
-            elif idx < c0:
-                for j in range(idx, c0):
-                    coefs[j] -= fc[jj]
-        w(f"    c[{k}] = {linear_form(coefs, names)};")
-        cand_coefs.append(coefs)
+        if literal:
+            den = 1
+            for c in cand[k]:
+                den = den * c.denominator // gcd(den, c.denominator)
+            ints = [c * den for c in cand[k]]
+            cand_den.append(den)
+            w(f"    c[{k}] = {lit(Fr(1, den))} * ({linear_form(ints, names)});")
+        else:
+            w(f"    c[{k}] = {linear_form(cand[k], names)};")
     w("  }")
     # transpose of the candidate map, for the adjoint: Dbar += C^T cbar
     w("  // adjoint of candidates: Dbar[j] += sum_k (d c_k / d D_j) cbar[k]")
     w("  static __device__ __forceinline__ void candidates_vjp(const double* cbar, double* Dbar) {")
+    if literal:
+        for k in range(nk):
+            w(f"    const double s{k} = {lit(Fr(1, cand_den[k]))} * cbar[{k}];")
+        src = [f"s{k}" for k in range(nk)]
+        mats = [[c * cand_den[k] for c in cand[k]] for k in range(nk)]
+    else:
+        src = [f"cbar[{k}]" for k in range(nk)]
+        mats = cand
     for j in range(K - 1):
-        col = [cand_coefs[k][j] for k in range(nk)]
+        col = [mats[k][j] for k in range(nk)]
         if any(c != 0 for c in col):
-            w(f"    Dbar[{j}] = {linear_form(col + [Fr(1)], [f'cbar[{k}]' for k in range(nk)] + [f'Dbar[{j}]'])};")
+            w(f"    Dbar[{j}] = {linear_form(col + [Fr(1)], src + [f'Dbar[{j}]'])};")
     w("  }")
     # betas
     w("  // smoothness measures beta_k (candidates) and beta_K (full stencil)")
     w("  static __device__ __forceinline__ void betas(const double* D, double* beta, double& betaK) {")
-    stencils = [(k, CANDIDATES[k]) for k in range(nk)] + [("K", (lo_full, K // 2))]
     for tag, (a, b) in stencils:
-        Q = diff_quadratic(a, b)
-        L, wts = ldl(Q)
-        n = len(Q)
-        first = a + c0  # index of the first difference of this stencil
+        first = a + K // 2 - 1  # index of the first difference of this stencil
+        n = b - a
         dn = [f"D[{first + j}]" for j in range(n)]
-        ys = []
-        for q in range(n):
-            coefs = [L[j][q] if j >= q else Fr(0) for j in range(n)]
-            ys.append(linear_form(coefs, dn))
-        var = f"b{tag}"
+        if literal:
+            rows = [(ints, wq * scale) for ints, wq in trows[tag]]
+            ys = [linear_form(ints, dn) for ints, _ in rows]
+            wts = [wq for _, wq in rows]
+        else:
+            Q = diff_quadratic(a, b)
+            L, wts = ldl(Q)
+            ys = [linear_form([L[j][q] if j >= q else Fr(0) for j in range(n)], dn) for q in range(n)]
         w("    {")
         for q in range(n):
             w(f"      const double y{q} = {ys[q]};")
-        acc = f"{lit(wts[0])} * (y0 * y0)"
-        expr = acc
+        expr = f"{lit(wts[0])} * (y0 * y0)"
         for q in range(1, n):
             expr = f"fma({lit(wts[q])} * y{q}, y{q}, {expr})"
         target = "betaK" if tag == "K" else f"beta[{tag}]"
@@ -240,8 +345,13 @@ def main(out=sys.stdout):
     out.write("// reconstruction in difference form.  Do not edit.\n")
     out.write("#pragma once\n\n")
     out.write("template <int K> struct TenoTables;\n\n")
-    out.write(emit(6) + "\n\n")
-    out.write(emit(8) + "\n")
+    # six points: the exact rationals as they come (the six-point kernels
+    # run at three or more wavefronts per SIMD, which hide the scalar moves
+    # of non-literal constants); eight points: literal-friendly forms (their
+    # kernels run at one wavefront per SIMD, where every constant moved into
+    # a scalar register costs an issue slot)
+    out.write(emit(6, literal=False) + "\n\n")
+    out.write(emit(8, literal=True) + "\n")
 
 
 if __name__ == "__main__":

@@ -128,9 +128,11 @@ __device__ __forceinline__ void teno_cutoff(const double (&D)[K - 1], const Teno
   T::betas(D, beta, betaK);
   const double tau = fabs(fma(fma(4.0, beta[0], beta[1] + beta[2]), -1.0 / 6.0, betaK));
   // gamma_k and the cutoff: chi_k = gamma_k / sum < C_T  <=>  gamma_k < C_T sum
+  // the tables may scale every beta by T::beta_scale; eps follows
+  constexpr double eps = kEps2x * T::beta_scale;
   double b[NK], binv[NK];
 #pragma unroll
-  for (int k = 0; k < NK; ++k) b[k] = beta[k] + kEps2x;
+  for (int k = 0; k < NK; ++k) b[k] = beta[k] + eps;
   rcp_pairs<NK>(b, binv);
   double g[NK];
   double sum = 0.0;

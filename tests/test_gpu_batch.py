@@ -213,7 +213,9 @@ def test_batched_4096_problems_graph_100_steps(T, orc):
     """The benchmark's batch: 4096 problems, n log-uniform in [256, 16384],
     TENO8-M-MP, 100 steps in one graph launch.  Checks: every problem equals
     the oracle run problem by problem on 12 sampled problems (tolerance
-    from the oracle's own one-ulp sensitivity over the run), conservation
+    from the oracle's own sensitivity to one-ulp differences at every step
+    of the run; per-step parity is test_batch_steps_match_the_oracle's),
+    conservation
     of every problem to round-off (no wave reaches an end in 100 steps),
     positivity, and the exact solution as a loose physics check."""
     import torch
@@ -255,18 +257,26 @@ def test_batched_4096_problems_graph_100_steps(T, orc):
         g = grid_of(n, dx[p], 1)
         print(f"[batch 4096] oracle run of problem {p} (n = {n})", flush=True)
 
-        def run(S):
+        def run(S, seed=None):
             tt = 0.0
-            for _ in range(100):
+            for k in range(100):
                 h = CFL / orc.max_wave_speed(S, g, GAMMA)
                 S = orc.rk3_step(S, g, 8, 1, 1e-7, GAMMA, h)
+                if seed is not None:  # rounding of another evaluation order, every step
+                    S = ulp_perturbed(S, seed=seed + 1000 * k)
                 tt += h
             return S, tt
 
         U0 = problem(U, plan, p)
         Uo, to = run(U0)
-        Up, _ = run(ulp_perturbed(U0, seed=int(p)))
-        tol, _ = conditioning_tol(Uo.T, Up.T, field_scale(Uo), factor=8.0)
+        # the oracle's own sensitivity to one-ulp differences at every step,
+        # over two seeds: the smoothness decisions in nearly flat regions
+        # are set by rounding (on any implementation), and over 100 steps
+        # such differences can move the state well above one step's rounding
+        Up1, _ = run(U0, seed=int(p))
+        Up2, _ = run(U0, seed=int(p) + 7)
+        spread = np.maximum(np.abs(Up1 - Uo), np.abs(Up2 - Uo))
+        tol, _ = conditioning_tol(Uo.T, (Uo + spread).T, field_scale(Uo), factor=8.0)
         err = np.abs(problem(Ug, plan, p) - Uo)
         assert np.all(err <= tol[:, None]), (p, (err / tol[:, None]).max())
         assert t[p] == pytest.approx(to, rel=1e-12)
