@@ -72,7 +72,7 @@ BYTES_PER_CELL_STEP = O.rk3_bytes_per_cell(5)
 # by 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB device copy reads
 # as).  They describe the kernels built from the sources whose digest is
 # TRAFFIC_SOURCE_DIGEST and are reported as null for any other build.
-TRAFFIC_SOURCE_DIGEST = "1f193b1f4a937ef78d8bdee58d4357c95617aa9c09229ace24613485338f9c6e"
+TRAFFIC_SOURCE_DIGEST = "4c690996e5be06e64ee40188562c1c042aac925d1dd0f161eeee143db1fd5cc3"
 MEASURED_TRAFFIC = {"sweep_x": 1.3425e9, "sweep_y": 2.0766e9, "sweep_z": 2.5240e9}
 # batched sweep, 4096 problems, averaged over the stages, per tile shape
 # (64x1, 128x1, 128x2, 256x1, 256x2, 512x1): smaller tiles re-read more halo
