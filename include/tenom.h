@@ -380,6 +380,23 @@ const char* tenom_last_error(void);
 int tenom_version(void);
 
 /*
+ * Kernel of the y and z sweeps, for every later call in the process (a
+ * test and tuning aid; both kernels compute the same face fluxes and cell
+ * updates, operation for operation, so the results are identical bit for
+ * bit).  TENOM_SWEEP_MARCH: each lane marches one x column along a segment
+ * of the line with its stencil in an LDS ring.  TENOM_SWEEP_TILE: a
+ * workgroup stages tiles of 8 x columns by a chunk of the line in LDS and
+ * walks the whole line.  TENOM_SWEEP_AUTO (the default): the tile kernel
+ * when the lines alone give at least 512 workgroups, else the march.
+ * Returns TENOM_EINVAL for any other value.  The setting is process-wide;
+ * calls made while another thread changes it may use either kernel.
+ */
+#define TENOM_SWEEP_AUTO 0
+#define TENOM_SWEEP_MARCH 1
+#define TENOM_SWEEP_TILE 2
+int tenom_set_sweep_kernel(int kind);
+
+/*
  * Kernel timing: while enabled, every kernel the compute calls launch is
  * bracketed by HIP events recorded on the same stream.  tenom_profile_read
  * synchronises those events and returns, per kernel kind, the number of

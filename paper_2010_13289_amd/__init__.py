@@ -37,7 +37,7 @@ SYMBOLS = (
     "tenom_batch_autotune", "tenom_batch_times", "tenom_batch_reset_times",
     "tenom_vjp_workspace_bytes", "tenom_flux_divergence_vjp", "tenom_rk3_vjp_workspace_bytes",
     "tenom_rk3_step_vjp", "tenom_rk3_step_stages", "tenom_rk3_step_vjp_stages", "tenom_rk3_step_cfl",
-    "tenom_static_scratch_bytes", "tenom_rk3_step_cfl_noalloc",
+    "tenom_static_scratch_bytes", "tenom_rk3_step_cfl_noalloc", "tenom_set_sweep_kernel",
 )
 
 
@@ -127,6 +127,7 @@ def lib() -> C.CDLL:
         L.tenom_strerror.restype = C.c_char_p
         L.tenom_last_error.restype = C.c_char_p
         L.tenom_profile_enable.argtypes = [C.c_int]
+        L.tenom_set_sweep_kernel.argtypes = [C.c_int]
         L.tenom_profile_read.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_int]
         ip = C.c_int
         L.tenom_batch_tile_shape.argtypes = [ip, C.POINTER(ip), C.POINTER(ip)]
@@ -321,6 +322,15 @@ def check_finite(U, grid, stream=None) -> bool:
         return False
     _check(rc)
     return True
+
+
+SWEEP_AUTO, SWEEP_MARCH, SWEEP_TILE = 0, 1, 2
+
+
+def set_sweep_kernel(kind: int):
+    """Kernel of the y and z sweeps for every later call (SWEEP_AUTO,
+    SWEEP_MARCH or SWEEP_TILE); both give the same bits."""
+    _check(lib().tenom_set_sweep_kernel(int(kind)))
 
 
 def profile_enable(on: bool = True):

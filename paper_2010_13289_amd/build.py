@@ -1,9 +1,10 @@
 """Build libtenom.so (HIP, gfx950) in-tree.
 
 Steps: regenerate csrc/teno_tables.h from gen_tables.py, compile the eight
-forward and the eight adjoint instantiation units (fields x K), the six
-batched-path units (one per tile shape) and the three C-ABI sources in
-parallel with hipcc, link them into paper_2010_13289_amd/libtenom.so.
+forward, the eight tile-sweep and the eight adjoint instantiation units
+(fields x K), the six batched-path units (one per tile shape) and the three
+C-ABI sources in parallel with hipcc, link them into
+paper_2010_13289_amd/libtenom.so.
 
     python -m paper_2010_13289_amd.build [--verbose]
 """
@@ -34,6 +35,10 @@ HIPCC_FLAGS = [
     # rounds the same way and gives the same bits
     "-ffp-contract=off",
 ]
+
+# the tile sweeps: no machine-level loop-invariant code motion (the face's
+# constants hoisted out of the chunk loop spill into vector-register lanes)
+TILE_FLAGS = ["-DTENOM_TILE_UNIT", "-mllvm", "-disable-machine-licm"]
 
 UNITS = [(nf, k) for nf in (1, 3, 4, 5) for k in (6, 8)]
 BATCH_TILES = 6  # tile shapes of the batched path (kTiles in teno_batch.h)
@@ -77,11 +82,12 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     cmds = []
     objs = []
     for nf, k in UNITS:
-        for unit in ("inst", "vjp"):
+        for unit in ("inst", "vjp", "tile"):
             obj = os.path.join(BUILD, f"{unit}_nf{nf}_k{k}.o")
             objs.append(obj)
-            cmds.append([hipcc, *HIPCC_FLAGS, f"-DTENOM_NF={nf}", f"-DTENOM_K={k}", "-c",
-                         os.path.join(CSRC, "tenom_inst.hip" if unit == "inst" else "tenom_vjp_inst.hip"), "-o", obj])
+            extra = TILE_FLAGS if unit == "tile" else []
+            cmds.append([hipcc, *HIPCC_FLAGS, *extra, f"-DTENOM_NF={nf}", f"-DTENOM_K={k}", "-c",
+                         os.path.join(CSRC, "tenom_vjp_inst.hip" if unit == "vjp" else "tenom_inst.hip"), "-o", obj])
     for t in range(BATCH_TILES):
         obj = os.path.join(BUILD, f"batch_tile{t}.o")
         objs.append(obj)

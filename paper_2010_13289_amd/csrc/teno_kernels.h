@@ -10,6 +10,10 @@
 //                  each thread forms one cell's divergence and applies the
 //                  epilogue.  A periodic row of <= 256 cells is one segment,
 //                  so every face and every cell is computed exactly once.
+//  k_sweep_tile    sweep along y or z (strided) for grids with many lines:
+//                  a workgroup takes TX adjacent x columns of one line and
+//                  walks it in chunks, each chunk a row sweep of a strided
+//                  tile staged in LDS.
 //  k_sweep_march   sweep along y or z (strided).  Each lane owns one x
 //                  column (coalesced 512-byte rows per wave; the block's
 //                  wavefronts take consecutive (line, segment) units) and marches
@@ -151,14 +155,16 @@ struct RowStage {
   static constexpr int NE = (NF == 1) ? 1 : 3 * NF + 1;  // U, F, lambda, Roe input
 };
 
-template <int NF, int K>
+// CS: staging-index step between consecutive cells of the sweep axis (1 in
+// the row sweep, the tile width in the tile sweep)
+template <int NF, int K, int CS = 1>
 struct StagedCells {
   const double* s;  // LDS: [NE][NC]
   int nc;           // row pitch of the staging array
   int c0;           // staging index of window cell 0
   __device__ __forceinline__ double at(int e, int c) const { return s[e * nc + c]; }
   __device__ __forceinline__ void cell(int m, double (&X)[NF], double (&F)[NF], double& lam) const {
-    const int c = c0 + m;
+    const int c = c0 + m * CS;
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
       X[q] = at(q, c);
@@ -167,14 +173,38 @@ struct StagedCells {
     lam = at(2 * NF, c);
   }
   __device__ __forceinline__ void roe(int sd, RoeIn<NF>& r) const {
-    const int c = c0 + K / 2 - 1 + sd;
+    const int c = c0 + (K / 2 - 1 + sd) * CS;
     r.rs = at(2 * NF + 1, c);
 #pragma unroll
     for (int d = 0; d < NF - 2; ++d) r.u[d] = at(2 * NF + 2 + d, c);
     r.H = at(3 * NF, c);
   }
-  __device__ __forceinline__ double value(int m) const { return at(0, c0 + m); }
+  __device__ __forceinline__ double value(int m) const { return at(0, c0 + m * CS); }
 };
+
+// Stage cell `cell` of the grid at staging index c: its state and, for the
+// Euler equations, its flux, signal speed and Roe inputs.
+template <int NF>
+__device__ __forceinline__ void stage_cell(double* stage, int nc, int c, const SweepParams<NF>& p, long N, long cell) {
+  double X[NF];
+#pragma unroll
+  for (int q = 0; q < NF; ++q) X[q] = p.U[p.fld[q] * N + cell];
+#pragma unroll
+  for (int q = 0; q < NF; ++q) stage[q * nc + c] = X[q];
+  if constexpr (NF > 1) {
+    double F[NF], lam;
+    RoeIn<NF> r;
+    cell_physics<NF>(X, p.fp.gamma, F, lam);
+    roe_input<NF>(X, p.fp.gamma, r);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) stage[(NF + q) * nc + c] = F[q];
+    stage[(2 * NF) * nc + c] = lam;
+    stage[(2 * NF + 1) * nc + c] = r.rs;
+#pragma unroll
+    for (int d = 0; d < NF - 2; ++d) stage[(2 * NF + 2 + d) * nc + c] = r.u[d];
+    stage[(3 * NF) * nc + c] = r.H;
+  }
+}
 
 // Waves per SIMD the row sweep is compiled for: three where the face fits
 // in 168 VGPRs without spilling (six points), else what the registers allow.
@@ -205,27 +235,7 @@ void k_sweep_row(SweepParams<NF> p) {
   __builtin_amdgcn_s_setprio(3);
 
   // stage cells c_begin - K/2 .. c_begin + nface + K/2 - 2
-  for (int c = t; c < nstage; c += 256) {
-    const long cell = cell_at(L, c_begin - K / 2 + c);
-    double X[NF];
-#pragma unroll
-    for (int q = 0; q < NF; ++q) X[q] = p.U[p.fld[q] * N + cell];
-#pragma unroll
-    for (int q = 0; q < NF; ++q) stage[q * NC + c] = X[q];
-    if constexpr (NF > 1) {
-      double F[NF], lam;
-      RoeIn<NF> r;
-      cell_physics<NF>(X, p.fp.gamma, F, lam);
-      roe_input<NF>(X, p.fp.gamma, r);
-#pragma unroll
-      for (int q = 0; q < NF; ++q) stage[(NF + q) * NC + c] = F[q];
-      stage[(2 * NF) * NC + c] = lam;
-      stage[(2 * NF + 1) * NC + c] = r.rs;
-#pragma unroll
-      for (int d = 0; d < NF - 2; ++d) stage[(2 * NF + 2 + d) * NC + c] = r.u[d];
-      stage[(3 * NF) * NC + c] = r.H;
-    }
-  }
+  for (int c = t; c < nstage; c += 256) stage_cell<NF>(stage, NC, c, p, N, cell_at(L, c_begin - K / 2 + c));
   __syncthreads();
 
   double F[NF];
@@ -259,6 +269,126 @@ void k_sweep_row(SweepParams<NF> p) {
 #pragma unroll
     for (int q = 0; q < NF; ++q) div[q] = (Fs[q * 257 + t] - Fs[q * 257 + r]) * p.inv_dx;
     epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile sweep (axis 1 or 2).  A 256-thread workgroup owns TX adjacent x
+// columns of one line along the axis and walks the whole line in chunks of
+// FJ = 256 / TX faces per column.  Each chunk is a row sweep on a strided
+// tile: its cells are staged in LDS (row r of the chunk at staging indices
+// r TX .. r TX + TX - 1) with their flux, signal speed and Roe inputs, each
+// thread computes one face, the fluxes go through LDS and each thread closes
+// the cell left of its face.  The last face of a chunk is handed to the next
+// chunk through LDS and face 0 of a periodic line is kept for its last cell,
+// so a line of M cells costs M faces (M + 1 when transmissive); only the
+// K - 1 halo rows of each chunk are staged twice.
+// ---------------------------------------------------------------------------
+constexpr int kTileColumns = 8;  // x columns per tile-sweep workgroup
+
+template <int NF, int K>
+struct SweepTile {
+  static constexpr int TX = kTileColumns;
+  static constexpr int FJ = 256 / TX;    // faces per column per chunk
+  static constexpr int ROWS = FJ + K - 1;  // staged cells per column per chunk
+};
+
+template <int NF, int K, int LIM, bool ADAPT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowOccupancy<NF, K>::WAVES)))
+void k_sweep_tile(SweepParams<NF> p, int axis) {
+  using S = SweepTile<NF, K>;
+  constexpr int TX = S::TX, FJ = S::FJ;
+  constexpr int NC = S::ROWS * TX;
+  constexpr int NE = RowStage<NF>::NE;
+  static_assert(256 % TX == 0, "whole columns per workgroup");
+  __shared__ double stage[NE * NC];
+  __shared__ double Fb[NF * FJ * TX];  // face f of the chunk at row f
+  __shared__ double Fc[2 * NF * TX];   // last face of chunk k at [k mod 2], for the next chunk
+  __shared__ double Fw[NF * TX];       // face 0 of a periodic line, the right face of its last cell
+  // tiles in XCD order: blocks b, b + 8, ... run on one XCD and take
+  // consecutive tiles, so the column groups of a line share that XCD's L2
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int xcd = b & 7, q8 = nb >> 3, r8 = nb & 7;
+  const int tile = xcd * q8 + min(xcd, r8) + (b >> 3);
+  const int ncg = (p.nx + TX - 1) / TX;
+  const int o = tile / ncg;  // line of the other axis
+  const int t = threadIdx.x;
+  const int col = t % TX, f = t / TX;
+  const int x = (tile % ncg) * TX + col;
+  const bool xin = x < p.nx;
+  const int xs = xin ? x : p.nx - 1;  // columns beyond the grid stage a real cell and store nothing
+  const long N = (long)p.nx * p.ny * p.nz;
+  Line L0;
+  if (axis == 1)
+    L0 = Line{xs + (long)p.nx * p.ny * o, p.nx, p.ny, p.bc};
+  else
+    L0 = Line{xs + (long)p.nx * o, (long)p.nx * p.ny, p.nz, p.bc};
+  const bool wrap = p.bc == 0;
+  const int nface = wrap ? p.n : p.n + 1;  // face j lies between cells j - 1 and j
+  const int nchunk = (nface + FJ - 1) / FJ;
+  // Phases of a chunk, each ended by a barrier: staging; faces (their
+  // fluxes into LDS); closing the cells, which reads the staged cells and
+  // the fluxes from LDS.  No value is held in registers across a barrier.
+  for (int k = 0; k < nchunk; ++k) {
+    // the line's cell addresses are formed anew in each chunk: hoisted out
+    // of the loop, their per-field parts would hold registers throughout
+    Line L = L0;
+    asm volatile("" : "+v"(L.base));
+    const int j0 = k * FJ;
+    const int nfk = min(FJ, nface - j0);  // faces of this chunk per column
+    const int nrow = nfk + K - 1;
+    __builtin_amdgcn_s_setprio(3);
+    for (int r = f; r < nrow; r += FJ) stage_cell<NF>(stage, NC, r * TX + col, p, N, cell_at(L, j0 - K / 2 + r));
+    __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
+    const int j = j0 + f;
+    const bool act = f < nfk;
+    if (act) {
+      double F[NF];
+      StagedCells<NF, K, TX> prov{stage, NC, f * TX + col};
+      uint32_t bits[2][NF];
+      face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F, bits);
+#pragma unroll
+      for (int q = 0; q < NF; ++q) Fb[(q * FJ + f) * TX + col] = F[q];
+      if (f == FJ - 1) {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) Fc[((k & 1) * NF + q) * TX + col] = F[q];
+      }
+      if (wrap && j == 0) {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) Fw[q * TX + col] = F[q];
+      }
+    }
+    __syncthreads();
+    __builtin_amdgcn_s_setprio(3);
+    // this thread closes cell j - 1 and, on a periodic line, the last cell
+    // (right of the last face) with face 0 as its right face
+    if (act && j >= 1 && xin) {
+      const long cell = L.base + (long)(j - 1) * L.stride;
+      EpiIn<NF> ein;
+      epi_load<NF>(p, N, cell, ein);
+      double us[NF], div[NF];
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        us[q] = stage[q * NC + (f + K / 2 - 1) * TX + col];
+        const double fl = f > 0 ? Fb[(q * FJ + f - 1) * TX + col] : Fc[(((k - 1) & 1) * NF + q) * TX + col];
+        div[q] = (fl - Fb[(q * FJ + f) * TX + col]) * p.inv_dx;
+      }
+      epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
+    }
+    if (wrap && act && j == nface - 1 && xin) {
+      const long cell = L.base + (long)j * L.stride;
+      EpiIn<NF> ein;
+      epi_load<NF>(p, N, cell, ein);
+      double us[NF], div[NF];
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        us[q] = stage[q * NC + (f + K / 2) * TX + col];
+        div[q] = (Fb[(q * FJ + f) * TX + col] - Fw[q * TX + col]) * p.inv_dx;
+      }
+      epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
+    }
+    __syncthreads();  // the next chunk's staging overwrites the cells read here
   }
 }
 
@@ -487,6 +617,35 @@ hipError_t launch_sweep(const SweepLaunch& a) {
     dim3 grid((a.nx + 63) / 64, (unsigned)gy, (unsigned)((ub + gy - 1) / gy));
     hipLaunchKernelGGL((k_sweep_march<NF, K, LIM, ADAPT>), grid, dim3(64, LINES), 0, a.stream, p, a.axis);
   }
+  return hipGetLastError();
+}
+
+// Tile sweep of axis 1 or 2: one workgroup per (line, group of TX columns).
+template <int NF, int K, int LIM, bool ADAPT>
+hipError_t launch_tile(const SweepLaunch& a) {
+  SweepParams<NF> p;
+  p.U = a.U;
+  p.R = a.R;
+  p.U0 = a.U0;
+  p.Uout = a.Uout;
+  p.a = a.a;
+  p.b = a.b;
+  p.dt = a.dt;
+  p.dtp = a.dtp;
+  p.mode = a.mode;
+  p.nx = a.nx;
+  p.ny = a.ny;
+  p.nz = a.nz;
+  p.bc = a.bc;
+  p.inv_dx = a.inv_dx;
+  p.fp = a.fp;
+  for (int q = 0; q < NF; ++q) p.fld[q] = a.fld[q];
+  if (a.axis != 1 && a.axis != 2) return hipErrorInvalidValue;
+  p.n = (a.axis == 1) ? a.ny : a.nz;
+  p.seg = p.n;
+  p.nseg = 1;
+  const long tiles = (long)((a.axis == 1) ? a.nz : a.ny) * ((a.nx + SweepTile<NF, K>::TX - 1) / SweepTile<NF, K>::TX);
+  hipLaunchKernelGGL((k_sweep_tile<NF, K, LIM, ADAPT>), dim3((unsigned)tiles), dim3(256), 0, a.stream, p, a.axis);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -108,11 +109,12 @@ FaceParams face_params(const tenom_grid* g, int axis, int limiter, double C_T, d
 using FacesFn = hipError_t (*)(int, int, const FacesLaunch&);
 using SweepFn = hipError_t (*)(int, int, const SweepLaunch&);
 
-bool pick(int nf, int K, FacesFn* f, SweepFn* s) {
+bool pick(int nf, int K, FacesFn* f, SweepFn* s, SweepFn* tile = nullptr) {
 #define TENOM_CASE(NF, KK)                      \
   if (nf == NF && K == KK) {                    \
     *f = tenom_faces_nf##NF##_k##KK;            \
     *s = tenom_sweep_nf##NF##_k##KK;            \
+    if (tile) *tile = tenom_tile_nf##NF##_k##KK; \
     return true;                                \
   }
   TENOM_CASE(1, 6)
@@ -210,6 +212,9 @@ int comb3(double* out, double c0, const double* x, double c1, const double* y1, 
   return e == hipSuccess ? TENOM_OK : hip_fail(e, "combination launch");
 }
 
+// kernel of the y and z sweeps (tenom_set_sweep_kernel)
+std::atomic<int> g_sweep_kernel{TENOM_SWEEP_AUTO};
+
 int march_segment(int n, int nx, int n_other) {
   static int env = -1;
   if (env < 0) {
@@ -236,14 +241,14 @@ int sweep(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma
           double* R, const double* U0, double* Uout, double a, double b, double dt, int mode, hipStream_t stream,
           const double* dtp = nullptr) {
   FacesFn ff;
-  SweepFn sf;
+  SweepFn sf, tf;
   const int nf = nfields(g);
   bool adaptive;
   const int K = scheme_K(scheme, &adaptive);
   int kind;
   double beta;
   limiter_kind(limiter, &kind, &beta);
-  if (!pick(nf, K, &ff, &sf)) return fail(TENOM_EUNSUPPORTED, "no kernel for %d fields, K = %d", nf, K);
+  if (!pick(nf, K, &ff, &sf, &tf)) return fail(TENOM_EUNSUPPORTED, "no kernel for %d fields, K = %d", nf, K);
   const Dims d = dims(g);
   SweepLaunch L;
   L.axis = axis;
@@ -263,13 +268,22 @@ int sweep(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma
   L.inv_dx = 1.0 / g->dx[axis];
   const int n_axis = axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
   L.seg = axis == 0 ? 0 : march_segment(n_axis, d.nx, axis == 1 ? d.nz : d.ny);
+  // y and z: the tile sweep walks whole lines, so it is taken when the lines
+  // alone give at least 512 workgroups (two per CU); else the march, which
+  // also splits lines into segments
+  bool tile = false;
+  if (axis != 0) {
+    const long tiles = (long)(axis == 1 ? d.nz : d.ny) * ((d.nx + kTileColumns - 1) / kTileColumns);
+    const int choice = g_sweep_kernel.load(std::memory_order_relaxed);
+    tile = choice == TENOM_SWEEP_TILE || (choice == TENOM_SWEEP_AUTO && tiles >= 512);
+  }
   field_map(g, axis, L.fld);
   L.fp = face_params(g, axis, limiter, C_T, gamma);
   L.stream = stream;
   hipError_t e;
   {
     ProfScope ps(1 + axis, stream);
-    e = sf(kind, adaptive ? 1 : 0, L);
+    e = (tile ? tf : sf)(kind, adaptive ? 1 : 0, L);
   }
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
   return TENOM_OK;
@@ -820,6 +834,13 @@ int tenom_rk3_step_vjp_stages(const tenom_grid* grid, int scheme, int limiter, d
   double* B2 = (double*)((char*)ws + 4 * state);
   double* contrib = (double*)((char*)ws + 5 * state);
   return rk3_vjp_core(grid, scheme, limiter, C_T, gamma, dt, U, U1, U2, Ubar, B1, B2, contrib, (hipStream_t)stream);
+}
+
+int tenom_set_sweep_kernel(int kind) {
+  g_err[0] = 0;
+  if (kind < TENOM_SWEEP_AUTO || kind > TENOM_SWEEP_TILE) return fail(TENOM_EINVAL, "sweep kernel %d not in {0, 1, 2}", kind);
+  g_sweep_kernel.store(kind, std::memory_order_relaxed);
+  return TENOM_OK;
 }
 
 int tenom_profile_enable(int on) {

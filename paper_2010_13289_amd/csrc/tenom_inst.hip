@@ -1,5 +1,6 @@
 // One instantiation unit: every limiter kind (and, for K = 8, the adaptive
-// cutoff) for TENOM_NF fields and K = TENOM_K.
+// cutoff) for TENOM_NF fields and K = TENOM_K; with TENOM_TILE_UNIT the
+// tile sweeps, else the face kernel and the row and march sweeps.
 #include <type_traits>
 
 #include "dispatch.h"
@@ -40,6 +41,19 @@ static hipError_t by_scheme(int lim, int adapt, const Launch& a, Fn fn) {
   return hipErrorInvalidValue;  // the adaptive cutoff is defined for K = 8 only
 }
 
+#ifdef TENOM_TILE_UNIT
+// The tile sweeps alone.  This unit is compiled without machine-level
+// loop-invariant code motion: hoisting the constants of the face out of
+// the chunk loop spills them into vector-register lanes that every face
+// reads back.
+#define TENOM_UNIT_TILE(nf, k) TENOM_NAME(tile, nf, k)
+#define TENOM_EXPAND_TILE(nf, k) TENOM_UNIT_TILE(nf, k)
+hipError_t TENOM_EXPAND_TILE(TENOM_NF, TENOM_K)(int lim, int adapt, const SweepLaunch& a) {
+  return by_scheme(lim, adapt, a, [](auto L, auto A, const SweepLaunch& x) {
+    return launch_tile<TENOM_NF, TENOM_K, decltype(L)::value, decltype(A)::value>(x);
+  });
+}
+#else
 hipError_t TENOM_EXPAND_FACES(TENOM_NF, TENOM_K)(int lim, int adapt, const FacesLaunch& a) {
   return by_scheme(lim, adapt, a, [](auto L, auto A, const FacesLaunch& x) {
     return launch_faces<TENOM_NF, TENOM_K, decltype(L)::value, decltype(A)::value>(x);
@@ -51,3 +65,4 @@ hipError_t TENOM_EXPAND_SWEEP(TENOM_NF, TENOM_K)(int lim, int adapt, const Sweep
     return launch_sweep<TENOM_NF, TENOM_K, decltype(L)::value, decltype(A)::value>(x);
   });
 }
+#endif

@@ -161,6 +161,15 @@ def test_scheme_and_limiter_ids(lib):
     assert lib.tenom_workspace_bytes(C.byref(g), 6 | 0x100) == 0
 
 
+def test_sweep_kernel_choice(lib):
+    """0 automatic, 1 march, 2 tile; anything else is rejected and leaves
+    the setting as it was (no device is touched)."""
+    for bad in (-1, 3, 99):
+        assert lib.tenom_set_sweep_kernel(bad) == -1
+    for ok in (1, 2, 0):
+        assert lib.tenom_set_sweep_kernel(ok) == 0
+
+
 def test_strerror_and_fields(lib):
     for code in (0, -1, -2, -3, -4, -5, -77):
         assert lib.tenom_strerror(code)
