@@ -175,14 +175,21 @@ __device__ __forceinline__ void teno_m_vjp_given(const double (&v)[K], const Ten
       // dm > 0: up = fmax(0, u1), u1 = fmin(u0, B), u0 = fmin(2 dm, 2 dp)
       // dm < 0: dn = fmin(0, w1), w1 = fmax(w0, B), w0 = fmax(2 dm, 2 dp)
       const bool pos = dm > 0.0, neg = dm < 0.0;
-      const double u0 = pos ? fmin(2.0 * dm, 2.0 * dp) : fmax(2.0 * dm, 2.0 * dp);
-      const double u1 = pos ? fmin(u0, B) : fmax(u0, B);
-      const bool live = pos ? !(0.0 >= u1) : (neg && !(0.0 <= u1));
-      const bool first = pos ? (u0 <= B) : (u0 >= B);
-      const bool pick_m = pos ? (2.0 * dm <= 2.0 * dp) : (2.0 * dm >= 2.0 * dp);
+      // both sides evaluated, then selected (nested or short-circuit
+      // conditionals can become branches)
+      const double mn0 = fmin(2.0 * dm, 2.0 * dp), mx0 = fmax(2.0 * dm, 2.0 * dp);
+      const double u0 = pos ? mn0 : mx0;
+      const double mn1 = fmin(u0, B), mx1 = fmax(u0, B);
+      const double u1 = pos ? mn1 : mx1;
+      const bool live_p = !(0.0 >= u1), live_n = neg & !(0.0 <= u1);
+      const bool live = pos ? live_p : live_n;
+      const bool first_p = u0 <= B, first_n = u0 >= B;
+      const bool first = pos ? first_p : first_n;
+      const bool pick_p = 2.0 * dm <= 2.0 * dp, pick_n = 2.0 * dm >= 2.0 * dp;
+      const bool pick_m = pos ? pick_p : pick_n;
       const double g = live ? sbar : 0.0;
-      dmbar += (first && pick_m) ? 2.0 * g : 0.0;
-      dpbar += (first && !pick_m) ? 2.0 * g : 0.0;
+      dmbar += (first & pick_m) ? 2.0 * g : 0.0;
+      dpbar += (first & !pick_m) ? 2.0 * g : 0.0;
       Bbar += first ? 0.0 : g;
       // B = (-2 D[C0-2] + 11 dm + 24 dp - 3 D[C0+1]) / 30
       const double b30 = Bbar * (1.0 / 30.0);

@@ -214,7 +214,8 @@ __device__ __forceinline__ uint32_t minmod_pick(const double* a, int na) {
     const bool p23 = pos ? (a[2] <= a[3]) : (a[2] >= a[3]);
     const double v01 = p01 ? a[0] : a[1], v23 = p23 ? a[2] : a[3];
     const bool pl = pos ? (v01 <= v23) : (v01 >= v23);
-    i = pl ? i : (p23 ? 2u : 3u);
+    const uint32_t i23 = p23 ? 2u : 3u;
+    i = pl ? i : i23;
   }
   return (pos || neg) ? i + 1u : 0u;
 }
@@ -223,18 +224,21 @@ template <int K, int LIM>
 __device__ __forceinline__ uint32_t mp_code(const double (&D)[K - 1], const MpState& s) {
   constexpr int C0 = K / 2 - 1;
   const double dp = D[C0];
+  // one select per statement: nested conditionals can become branches
   uint32_t lo, hi;
   {
     const double m1 = fmin(0.0, dp), A1 = fmin(m1, s.md);
     const double m2 = fmin(0.0, s.ul), A2 = fmin(m2, s.lc);
-    lo = (A1 >= A2) ? ((m1 <= s.md) ? (!(0.0 <= dp) ? 1u : 0u) : 2u)
-                    : ((m2 <= s.lc) ? (!(0.0 <= s.ul) ? 3u : 0u) : 4u);
+    const uint32_t c1 = (0.0 <= dp) ? 0u : 1u, c2 = (0.0 <= s.ul) ? 0u : 3u;
+    const uint32_t l1 = (m1 <= s.md) ? c1 : 2u, l2 = (m2 <= s.lc) ? c2 : 4u;
+    lo = (A1 >= A2) ? l1 : l2;
   }
   {
     const double n1 = fmax(0.0, dp), B1 = fmax(n1, s.md);
     const double n2 = fmax(0.0, s.ul), B2 = fmax(n2, s.lc);
-    hi = (B1 <= B2) ? ((n1 >= s.md) ? (!(0.0 >= dp) ? 1u : 0u) : 2u)
-                    : ((n2 >= s.lc) ? (!(0.0 >= s.ul) ? 3u : 0u) : 4u);
+    const uint32_t c1 = (0.0 >= dp) ? 0u : 1u, c2 = (0.0 >= s.ul) ? 0u : 3u;
+    const uint32_t h1 = (n1 >= s.md) ? c1 : 2u, h2 = (n2 >= s.lc) ? c2 : 4u;
+    hi = (B1 <= B2) ? h1 : h2;
   }
   constexpr int NA = (LIM == LIM_MP) ? 4 : 2;
   const uint32_t r = minmod_pick(s.aR, NA), l = minmod_pick(s.aL, NA);
@@ -295,7 +299,9 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
       bits |= mp_code<K, LIM>(D, ms) << 20;
 #pragma unroll
       for (int k = 0; k < NK; ++k) {
-        const uint32_t sel = smooth[k] ? 0u : (!(fmax(c[k], lo) <= hi) ? 2u : (c[k] >= lo ? 0u : 1u));
+        const uint32_t in_lo = (c[k] >= lo) ? 0u : 1u;
+        const uint32_t clip = (fmax(c[k], lo) <= hi) ? in_lo : 2u;
+        const uint32_t sel = smooth[k] ? 0u : clip;
         bits |= sel << (8 + 2 * k);
       }
     }
@@ -309,16 +315,26 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
     const double B = tvd5_b<K>(D);
     const double up = fmax(0.0, fmin(fmin(2.0 * dm, 2.0 * dp), B));
     const double dn = fmin(0.0, fmax(fmax(2.0 * dm, 2.0 * dp), B));
-    ftvd = 0.5 * (dm > 0.0 ? up : (dm < 0.0 ? dn : 0.0));
+    const double dn0 = (dm < 0.0) ? dn : 0.0;
+    ftvd = 0.5 * ((dm > 0.0) ? up : dn0);
     if constexpr (FLAGS) {
       // the same choices as the fmin/fmax chains, first argument on a tie
       const bool pos = dm > 0.0, neg = dm < 0.0;
-      const double u0 = pos ? fmin(2.0 * dm, 2.0 * dp) : fmax(2.0 * dm, 2.0 * dp);
-      const double u1 = pos ? fmin(u0, B) : fmax(u0, B);
-      const bool live = pos ? !(0.0 >= u1) : (neg && !(0.0 <= u1));
-      const bool first = pos ? (u0 <= B) : (u0 >= B);
-      const bool pick_m = pos ? (2.0 * dm <= 2.0 * dp) : (2.0 * dm >= 2.0 * dp);
-      bits |= (live ? (first ? (pick_m ? 1u : 2u) : 3u) : 0u) << 8;
+      // both sides evaluated, then selected (nested or short-circuit
+      // conditionals can become branches)
+      const double mn0 = fmin(2.0 * dm, 2.0 * dp), mx0 = fmax(2.0 * dm, 2.0 * dp);
+      const double u0 = pos ? mn0 : mx0;
+      const double mn1 = fmin(u0, B), mx1 = fmax(u0, B);
+      const double u1 = pos ? mn1 : mx1;
+      const bool live_p = !(0.0 >= u1), live_n = neg & !(0.0 <= u1);
+      const bool live = pos ? live_p : live_n;
+      const bool first_p = u0 <= B, first_n = u0 >= B;
+      const bool first = pos ? first_p : first_n;
+      const bool pick_p = 2.0 * dm <= 2.0 * dp, pick_n = 2.0 * dm >= 2.0 * dp;
+      const bool pick_m = pos ? pick_p : pick_n;
+      const uint32_t pm = pick_m ? 1u : 2u;
+      const uint32_t pf = first ? pm : 3u;
+      bits |= (live ? pf : 0u) << 8;
     }
   } else if constexpr (LIM == LIM_VA) {
     const double phi = 2.0 * dp * dm * rcp(va_den(dm, dp));
