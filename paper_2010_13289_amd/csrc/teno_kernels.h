@@ -312,81 +312,98 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
   const int tile = xcd * q8 + min(xcd, r8) + (b >> 3);
   const int ncg = (p.nx + TX - 1) / TX;
   const int o = tile / ncg;  // line of the other axis
-  const int t = threadIdx.x;
-  const int col = t % TX, f = t / TX;
-  const int x = (tile % ncg) * TX + col;
-  const bool xin = x < p.nx;
-  const int xs = xin ? x : p.nx - 1;  // columns beyond the grid stage a real cell and store nothing
   const long N = (long)p.nx * p.ny * p.nz;
-  Line L0;
-  if (axis == 1)
-    L0 = Line{xs + (long)p.nx * p.ny * o, p.nx, p.ny, p.bc};
-  else
-    L0 = Line{xs + (long)p.nx * o, (long)p.nx * p.ny, p.nz, p.bc};
   const bool wrap = p.bc == 0;
   const int nface = wrap ? p.n : p.n + 1;  // face j lies between cells j - 1 and j
   const int nchunk = (nface + FJ - 1) / FJ;
   // Phases of a chunk, each ended by a barrier: staging; faces (their
   // fluxes into LDS); closing the cells, which reads the staged cells and
   // the fluxes from LDS.  No value is held in registers across a barrier.
+  // The thread's column and line address are formed anew in each phase from
+  // an opaque copy of the thread index: hoisted out of the loop they would
+  // hold registers through the face computation.
+  struct Where {
+    int col, f;
+    bool xin;
+    Line L;
+  };
+  auto where = [&]() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    Where w;
+    w.col = t % TX;
+    w.f = t / TX;
+    const int x = (tile % ncg) * TX + w.col;
+    w.xin = x < p.nx;
+    const int xs = w.xin ? x : p.nx - 1;  // columns beyond the grid stage a real cell and store nothing
+    w.L = (axis == 1) ? Line{xs + (long)p.nx * p.ny * o, p.nx, p.ny, p.bc}
+                      : Line{xs + (long)p.nx * o, (long)p.nx * p.ny, p.nz, p.bc};
+    return w;
+  };
   for (int k = 0; k < nchunk; ++k) {
-    // the line's cell addresses are formed anew in each chunk: hoisted out
-    // of the loop, their per-field parts would hold registers throughout
-    Line L = L0;
-    asm volatile("" : "+v"(L.base));
     const int j0 = k * FJ;
     const int nfk = min(FJ, nface - j0);  // faces of this chunk per column
-    const int nrow = nfk + K - 1;
     __builtin_amdgcn_s_setprio(3);
-    for (int r = f; r < nrow; r += FJ) stage_cell<NF>(stage, NC, r * TX + col, p, N, cell_at(L, j0 - K / 2 + r));
+    {
+      const Where w = where();
+      for (int r = w.f; r < nfk + K - 1; r += FJ)
+        stage_cell<NF>(stage, NC, r * TX + w.col, p, N, cell_at(w.L, j0 - K / 2 + r));
+    }
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
-    const int j = j0 + f;
-    const bool act = f < nfk;
-    if (act) {
-      double F[NF];
-      StagedCells<NF, K, TX> prov{stage, NC, f * TX + col};
-      uint32_t bits[2][NF];
-      face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F, bits);
+    {
+      const Where w = where();
+      const int f = w.f, col = w.col, j = j0 + f;
+      if (f < nfk) {
+        double F[NF];
+        StagedCells<NF, K, TX> prov{stage, NC, f * TX + col};
+        uint32_t bits[2][NF];
+        face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F, bits);
 #pragma unroll
-      for (int q = 0; q < NF; ++q) Fb[(q * FJ + f) * TX + col] = F[q];
-      if (f == FJ - 1) {
+        for (int q = 0; q < NF; ++q) Fb[(q * FJ + f) * TX + col] = F[q];
+        if (f == FJ - 1) {
 #pragma unroll
-        for (int q = 0; q < NF; ++q) Fc[((k & 1) * NF + q) * TX + col] = F[q];
-      }
-      if (wrap && j == 0) {
+          for (int q = 0; q < NF; ++q) Fc[((k & 1) * NF + q) * TX + col] = F[q];
+        }
+        if (wrap && j == 0) {
 #pragma unroll
-        for (int q = 0; q < NF; ++q) Fw[q * TX + col] = F[q];
+          for (int q = 0; q < NF; ++q) Fw[q * TX + col] = F[q];
+        }
       }
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(3);
-    // this thread closes cell j - 1 and, on a periodic line, the last cell
-    // (right of the last face) with face 0 as its right face
-    if (act && j >= 1 && xin) {
-      const long cell = L.base + (long)(j - 1) * L.stride;
-      EpiIn<NF> ein;
-      epi_load<NF>(p, N, cell, ein);
-      double us[NF], div[NF];
+    {
+      // this thread closes cell j - 1 and, on a periodic line, the last cell
+      // (right of the last face) with face 0 as its right face
+      const Where w = where();
+      const int f = w.f, col = w.col, j = j0 + f;
+      const bool act = f < nfk && w.xin;
+      if (act && j >= 1) {
+        const long cell = w.L.base + (long)(j - 1) * w.L.stride;
+        EpiIn<NF> ein;
+        epi_load<NF>(p, N, cell, ein);
+        double us[NF], div[NF];
 #pragma unroll
-      for (int q = 0; q < NF; ++q) {
-        us[q] = stage[q * NC + (f + K / 2 - 1) * TX + col];
-        const double fl = f > 0 ? Fb[(q * FJ + f - 1) * TX + col] : Fc[(((k - 1) & 1) * NF + q) * TX + col];
-        div[q] = (fl - Fb[(q * FJ + f) * TX + col]) * p.inv_dx;
+        for (int q = 0; q < NF; ++q) {
+          us[q] = stage[q * NC + (f + K / 2 - 1) * TX + col];
+          const double fl = f > 0 ? Fb[(q * FJ + f - 1) * TX + col] : Fc[(((k - 1) & 1) * NF + q) * TX + col];
+          div[q] = (fl - Fb[(q * FJ + f) * TX + col]) * p.inv_dx;
+        }
+        epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
       }
-      epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
-    }
-    if (wrap && act && j == nface - 1 && xin) {
-      const long cell = L.base + (long)j * L.stride;
-      EpiIn<NF> ein;
-      epi_load<NF>(p, N, cell, ein);
-      double us[NF], div[NF];
+      if (wrap && act && j == nface - 1) {
+        const long cell = w.L.base + (long)j * w.L.stride;
+        EpiIn<NF> ein;
+        epi_load<NF>(p, N, cell, ein);
+        double us[NF], div[NF];
 #pragma unroll
-      for (int q = 0; q < NF; ++q) {
-        us[q] = stage[q * NC + (f + K / 2) * TX + col];
-        div[q] = (Fb[(q * FJ + f) * TX + col] - Fw[q * TX + col]) * p.inv_dx;
+        for (int q = 0; q < NF; ++q) {
+          us[q] = stage[q * NC + (f + K / 2) * TX + col];
+          div[q] = (Fb[(q * FJ + f) * TX + col] - Fw[q * TX + col]) * p.inv_dx;
+        }
+        epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
       }
-      epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
     }
     __syncthreads();  // the next chunk's staging overwrites the cells read here
   }
