@@ -375,34 +375,40 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
     __builtin_amdgcn_s_setprio(3);
     {
       // this thread closes cell j - 1 and, on a periodic line, the last cell
-      // (right of the last face) with face 0 as its right face
+      // (right of the last face) with face 0 as its right face.  The
+      // epilogue's parameters are read anew through an opaque pointer to the
+      // argument: held from the kernel's start they would be spilled across
+      // the face and read back lane by lane.
+      long off = 0;
+      asm volatile("" : "+s"(off));
+      const SweepParams<NF>& pe = *(const SweepParams<NF>*)((const char*)&p + off);
       const Where w = where();
       const int f = w.f, col = w.col, j = j0 + f;
       const bool act = f < nfk && w.xin;
       if (act && j >= 1) {
         const long cell = w.L.base + (long)(j - 1) * w.L.stride;
         EpiIn<NF> ein;
-        epi_load<NF>(p, N, cell, ein);
+        epi_load<NF>(pe, N, cell, ein);
         double us[NF], div[NF];
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
           us[q] = stage[q * NC + (f + K / 2 - 1) * TX + col];
           const double fl = f > 0 ? Fb[(q * FJ + f - 1) * TX + col] : Fc[(((k - 1) & 1) * NF + q) * TX + col];
-          div[q] = (fl - Fb[(q * FJ + f) * TX + col]) * p.inv_dx;
+          div[q] = (fl - Fb[(q * FJ + f) * TX + col]) * pe.inv_dx;
         }
-        epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
+        epi_store<NF>(pe, N, cell, div, ein, us, epi_dt(pe));
       }
       if (wrap && act && j == nface - 1) {
         const long cell = w.L.base + (long)j * w.L.stride;
         EpiIn<NF> ein;
-        epi_load<NF>(p, N, cell, ein);
+        epi_load<NF>(pe, N, cell, ein);
         double us[NF], div[NF];
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
           us[q] = stage[q * NC + (f + K / 2) * TX + col];
-          div[q] = (Fb[(q * FJ + f) * TX + col] - Fw[q * TX + col]) * p.inv_dx;
+          div[q] = (Fb[(q * FJ + f) * TX + col] - Fw[q * TX + col]) * pe.inv_dx;
         }
-        epi_store<NF>(p, N, cell, div, ein, us, epi_dt(p));
+        epi_store<NF>(pe, N, cell, div, ein, us, epi_dt(pe));
       }
     }
     __syncthreads();  // the next chunk's staging overwrites the cells read here
