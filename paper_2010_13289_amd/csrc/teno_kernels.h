@@ -206,11 +206,12 @@ __device__ __forceinline__ void stage_cell(double* stage, int nc, int c, const S
   }
 }
 
-// Waves per SIMD the row sweep is compiled for: three where the face fits
-// in 168 VGPRs without spilling (six points), else what the registers allow.
+// Waves per SIMD the row and tile sweeps are compiled for: three where the
+// face fits in 168 VGPRs without spilling (six points), two at eight points
+// (at most 256 VGPRs; every eight-point variant fits without spilling).
 template <int NF, int K>
 struct RowOccupancy {
-  static constexpr int WAVES = (K == 6) ? 3 : 1;
+  static constexpr int WAVES = (K == 6) ? 3 : 2;
 };
 
 template <int NF, int K, int LIM, bool ADAPT>
