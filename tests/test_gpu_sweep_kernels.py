@@ -111,3 +111,25 @@ def test_tile_against_the_oracle(T, orc, spec):
     Uo = orc.rk3_step(U, grid, K, lim, C_T, GAMMA, dt)
     excl = rk3_band_cells(orc, U, grid, K, lim, C_T, dt)
     assert_close_fields(Ug, Uo, exclude=excl, what=f"{spec[0]} RK3 step, tile sweeps")
+
+
+def test_automatic_choice_at_64_cubed_against_the_oracle(T, orc):
+    """At 64^3 the lines of y and z give 512 tile workgroups, so the automatic
+    choice runs the tile sweeps: the divergence of a seeded state against
+    the oracle over every cell outside the cutoff band (1e-12 of each field's
+    largest magnitude)."""
+    from parity import band_faces, faces_to_cells
+    shape = (64, 64, 64)
+    grid = dict(ndim=3, n=[64, 64, 64], dx=[0.05, 0.07, 0.06], bc=[0, 1, 0], system=1)
+    U = W.random_euler_state(shape, seed=57, kind="mixed")
+    K, lim, C_T = 6, 1, 1e-5
+    print("[automatic choice] 64^3 divergence", flush=True)
+    T.set_sweep_kernel(T.SWEEP_AUTO)
+    dg = to_host(T.flux_divergence(to_dev(U), grid, K, lim, C_T, GAMMA))
+    do = orc.flux_divergence(U, grid, K, lim, C_T, GAMMA)
+    excl = np.zeros(shape, dtype=bool)
+    for axis in range(3):
+        _, _, bd = orc.reconstruct_faces(U, grid, K, lim, C_T, GAMMA, axis)
+        excl |= faces_to_cells(band_faces(bd), 2 - axis, 64, grid["bc"][axis] == 0, 1)
+    assert excl.mean() < 0.01
+    assert_close_fields(dg, do, exclude=excl, what="64^3 dU/dt, automatic sweep kernels")
