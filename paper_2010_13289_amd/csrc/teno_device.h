@@ -263,14 +263,17 @@ constexpr double kVaDenMin = 2.2250738585072014e-308;
 
 __device__ __forceinline__ double va_den(double dm, double dp) { return fmax(fma(dp, dp, dm * dm), kVaDenMin); }
 
-// One TENO-M reconstruction (Secs. 2.2-3.3).  When FLAGS, `bits` receives
+// One TENO-M reconstruction (Secs. 2.2-3.3).  With SKIP, a wavefront in
+// which every candidate of every lane is smooth skips the limiter, which only
+// reaches nonsmooth candidates: the assembly then adds the same terms in the
+// same order, so the result has the same bits.  When FLAGS, `bits` receives
 // delta_k (1 = smooth) in bit k and, above bit 7, the limiter's decisions
 // (what the adjoint with frozen branches needs): MP limiters, per candidate
 // k the median's choice in bits 8 + 2k (0 the candidate, 1 the lower bound,
 // 2 the upper) and mp_code in bits 20..31; TVD minmod, the minmod's pick in
 // bits 8..9 (0 none, 1 d-, 2 d+); TVD5, bits 8..9 (0 none, 1 2d-, 2 2d+,
 // 3 the fifth-order slope).
-template <int K, int LIM, bool FLAGS, bool ADAPT>
+template <int K, int LIM, bool FLAGS, bool ADAPT, bool SKIP = false>
 __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams& tp, uint32_t& bits) {
   using T = TenoTables<K>;
   constexpr int NK = K - 2;
@@ -285,6 +288,18 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
   T::candidates(D, c);
   bool smooth[NK];
   teno_cutoff<K, ADAPT>(D, tp, smooth);
+
+  if constexpr (SKIP && !FLAGS && LIM != LIM_TENO) {
+    bool rough = false;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) rough |= !smooth[k];
+    if (__builtin_amdgcn_ballot_w64(rough) == 0) {  // uniform across the wavefront
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) acc = fma(T::d(k), c[k], acc);
+      return v[C0] + acc;
+    }
+  }
 
   // limiter on the nonsmooth candidates (Eq. mp_flux), relative to v_i
   const double dm = D[C0 - 1];  // f_i - f_{i-1}
@@ -538,27 +553,66 @@ __device__ __forceinline__ void euler_face(P& prov, double gamma, const TenoPara
     w[NF - 1] = 0.5 * fma(-Bn, cinv, A);
   };
 
-  // stencil cells: characteristic projections of U and F, Rusanov alpha
-  double W[K][NF], G[K][NF];
-  double alpha = 0.0;
-#pragma unroll
-  for (int m = 0; m < K; ++m) {
-    double X[NF], F[NF], lam;
-    prov.cell(m, X, F, lam);
-    alpha = fmax(alpha, lam);
-    project(X, W[m]);
-    project(F, G[m]);
-  }
-
-  // Rusanov split and two mirrored TENO-M reconstructions per field
   double fc[NF];
+  if constexpr (!FLAGS && P::kReread && LIM != LIM_TENO) {
+    // Group by group of fields from the staged cells: each group's stencil
+    // values are projected from a fresh read of the cells (only the group's
+    // rows of the eigenvectors survive), so that no array of every field's
+    // projections stays live across the limiter skips of the
+    // reconstructions.  The same operations in the same order as below: the
+    // same bits.
+    double alpha = 0.0;
 #pragma unroll
-  for (int q = 0; q < NF; ++q) {
-    double vp[K], vm[K];
+    for (int m = 0; m < K; ++m) alpha = fmax(alpha, prov.speed(m));
+    auto group = [&](uint32_t mask) {
+      const P pq = prov.fresh();
+      double vp[NF][K], vm[NF][K];
 #pragma unroll
-    for (int m = 0; m < K; ++m) lf_split2(G[m][q], alpha, W[m][q], vp[m], vm[K - 1 - m]);
-    bits[0][q] = bits[1][q] = 0u;
-    fc[q] = 0.5 * (teno_m<K, LIM, FLAGS, ADAPT>(vp, tp, bits[0][q]) + teno_m<K, LIM, FLAGS, ADAPT>(vm, tp, bits[1][q]));
+      for (int m = 0; m < K; ++m) {
+        double X[NF], F[NF], w[NF], g[NF];
+        pq.state_flux(m, X, F);
+        project(X, w);
+        project(F, g);
+#pragma unroll
+        for (int q = 0; q < NF; ++q)
+          if ((mask >> q) & 1u) lf_split2(g[q], alpha, w[q], vp[q][m], vm[q][K - 1 - m]);
+      }
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        if ((mask >> q) & 1u) {
+          bits[0][q] = bits[1][q] = 0u;
+          fc[q] = 0.5 * (teno_m<K, LIM, false, ADAPT, true>(vp[q], tp, bits[0][q]) +
+                         teno_m<K, LIM, false, ADAPT, true>(vm[q], tp, bits[1][q]));
+        }
+      }
+    };
+    // the acoustic and entropy fields share their projection's terms: one
+    // group; each shear field alone
+    group(3u | (1u << (NF - 1)));
+#pragma unroll
+    for (int q = 2; q < NF - 1; ++q) group(1u << q);
+  } else {
+    // stencil cells: characteristic projections of U and F, Rusanov alpha
+    double W[K][NF], G[K][NF];
+    double alpha = 0.0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      double X[NF], F[NF], lam;
+      prov.cell(m, X, F, lam);
+      alpha = fmax(alpha, lam);
+      project(X, W[m]);
+      project(F, G[m]);
+    }
+
+    // Rusanov split and two mirrored TENO-M reconstructions per field
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      double vp[K], vm[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) lf_split2(G[m][q], alpha, W[m][q], vp[m], vm[K - 1 - m]);
+      bits[0][q] = bits[1][q] = 0u;
+      fc[q] = 0.5 * (teno_m<K, LIM, FLAGS, ADAPT>(vp, tp, bits[0][q]) + teno_m<K, LIM, FLAGS, ADAPT>(vm, tp, bits[1][q]));
+    }
   }
 
   // back to conservative variables with the right eigenvectors
@@ -590,7 +644,8 @@ __device__ __forceinline__ void scalar_face(P& prov, double a, const TenoParams&
     lf_split2(a * u, alpha, u, vp[m], vm[K - 1 - m]);  // f- side stored mirrored
   }
   bits[0] = bits[1] = 0u;
-  F = 0.5 * (teno_m<K, LIM, FLAGS, ADAPT>(vp, tp, bits[0]) + teno_m<K, LIM, FLAGS, ADAPT>(vm, tp, bits[1]));
+  constexpr bool SKIP = P::kReread;
+  F = 0.5 * (teno_m<K, LIM, FLAGS, ADAPT, SKIP>(vp, tp, bits[0]) + teno_m<K, LIM, FLAGS, ADAPT, SKIP>(vm, tp, bits[1]));
 }
 
 struct FaceParams {
@@ -619,6 +674,7 @@ __device__ __forceinline__ void face_flux(P& prov, const FaceParams& fp, double 
 // straight from global memory (face j of a line)
 template <int NF, int K>
 struct GlobalCells {
+  static constexpr bool kReread = false;  // re-reads would go to memory
   const double* __restrict__ U;
   long N;
   const int* fld;

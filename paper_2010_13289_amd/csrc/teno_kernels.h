@@ -156,13 +156,34 @@ struct RowStage {
 };
 
 // CS: staging-index step between consecutive cells of the sweep axis (1 in
-// the row sweep, the tile width in the tile sweep)
-template <int NF, int K, int CS = 1>
+// the row sweep, the tile width in the tile sweep).  REREAD: the Euler face
+// projects its stencil group by group of fields from fresh reads of the
+// cells and lets wavefronts whose candidates are all smooth skip the limiter
+// (worth it where a wavefront's faces form a compact patch, as in the tile
+// sweep: a discontinuity then crosses few wavefronts).
+template <int NF, int K, int CS = 1, bool REREAD = false>
 struct StagedCells {
+  static constexpr bool kReread = REREAD;  // the face reads the cells again per group of fields
   const double* s;  // LDS: [NE][NC]
   int nc;           // row pitch of the staging array
   int c0;           // staging index of window cell 0
   __device__ __forceinline__ double at(int e, int c) const { return s[e * nc + c]; }
+  // the same provider, its position hidden from the compiler, so that reads
+  // through it are not merged with earlier reads of the same cells
+  __device__ __forceinline__ StagedCells fresh() const {
+    int c = c0;
+    asm volatile("" : "+v"(c));
+    return StagedCells<NF, K, CS, REREAD>{s, nc, c};
+  }
+  __device__ __forceinline__ void state_flux(int m, double (&X)[NF], double (&F)[NF]) const {
+    const int c = c0 + m * CS;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      X[q] = at(q, c);
+      F[q] = at(NF + q, c);
+    }
+  }
+  __device__ __forceinline__ double speed(int m) const { return at(2 * NF, c0 + m * CS); }
   __device__ __forceinline__ void cell(int m, double (&X)[NF], double (&F)[NF], double& lam) const {
     const int c = c0 + m * CS;
 #pragma unroll
@@ -357,7 +378,7 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
       const int f = w.f, col = w.col, j = j0 + f;
       if (f < nfk) {
         double F[NF];
-        StagedCells<NF, K, TX> prov{stage, NC, f * TX + col};
+        StagedCells<NF, K, TX, true> prov{stage, NC, f * TX + col};
         uint32_t bits[2][NF];
         face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F, bits);
 #pragma unroll
@@ -431,6 +452,7 @@ struct RoeCarry<1> {};
 
 template <int NF, int K>
 struct RingCells {
+  static constexpr bool kReread = false;  // the cell flux is recomputed per read
   // values per ring slot: the cell's state and, for the Euler equations, its
   // signal speed (computed once, when the cell enters the window)
   static constexpr int NR = (NF > 1) ? NF + 1 : NF;
