@@ -380,14 +380,17 @@ const char* tenom_last_error(void);
 int tenom_version(void);
 
 /*
- * Kernel of the y and z sweeps, for every later call in the process (a
- * test and tuning aid; both kernels compute the same face fluxes and cell
- * updates, operation for operation, so the results are identical bit for
- * bit).  TENOM_SWEEP_MARCH: each lane marches one x column along a segment
- * of the line with its stencil in an LDS ring.  TENOM_SWEEP_TILE: a
- * workgroup stages tiles of 8 x columns by a chunk of the line in LDS and
- * walks the whole line.  TENOM_SWEEP_AUTO (the default): the tile kernel
- * when the lines alone give at least 512 workgroups, else the march.
+ * Kernel of the sweeps, for every later call in the process (a test and
+ * tuning aid; the kernels compute the same face fluxes and cell updates,
+ * operation for operation, so the results are identical bit for bit).
+ * TENOM_SWEEP_MARCH: the line kernels; x rows are staged in LDS by
+ * segments of 256 cells, and along y and z each lane marches one x column
+ * along a segment of the line with its stencil in an LDS ring.
+ * TENOM_SWEEP_TILE: a workgroup stages tiles of 8 adjacent lines (x columns
+ * for y and z, y rows for x) by a chunk of the line in LDS and walks the
+ * lines whole.  TENOM_SWEEP_AUTO (the default): per axis, the tile kernel
+ * when the lines alone give at least 512 workgroups (along x only for the
+ * six-point schemes), else the line kernel.
  * Returns TENOM_EINVAL for any other value.  The setting is process-wide;
  * calls made while another thread changes it may use either kernel.
  */

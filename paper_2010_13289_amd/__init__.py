@@ -328,8 +328,8 @@ SWEEP_AUTO, SWEEP_MARCH, SWEEP_TILE = 0, 1, 2
 
 
 def set_sweep_kernel(kind: int):
-    """Kernel of the y and z sweeps for every later call (SWEEP_AUTO,
-    SWEEP_MARCH or SWEEP_TILE); both give the same bits."""
+    """Kernel of the sweeps for every later call (SWEEP_AUTO, SWEEP_MARCH:
+    the line kernels, or SWEEP_TILE); all give the same bits."""
     _check(lib().tenom_set_sweep_kernel(int(kind)))
 
 

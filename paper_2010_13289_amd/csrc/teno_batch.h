@@ -93,7 +93,7 @@ __global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
   for (int f = 0; f < FPT; ++f) {
     const int j = t + f * TPB;
     if (j < nface) {
-      StagedCells<NF, K> prov{stage, NC, j};
+      StagedCells<NF, K, 1, true> prov{stage, NC, j};
       uint32_t bits[2][NF];
       face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F[f], bits);
     }

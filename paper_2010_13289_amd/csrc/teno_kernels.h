@@ -159,8 +159,10 @@ struct RowStage {
 // the row sweep, the tile width in the tile sweep).  REREAD: the Euler face
 // projects its stencil group by group of fields from fresh reads of the
 // cells and lets wavefronts whose candidates are all smooth skip the limiter
-// (worth it where a wavefront's faces form a compact patch, as in the tile
-// sweep: a discontinuity then crosses few wavefronts).
+// (worth it where most wavefronts see only smooth data: the tile sweep's
+// 8 x 8 patches of faces, which a discontinuity crosses far less often than
+// the row sweep's strips of 64, and the batched 1D problems' constant
+// states).
 template <int NF, int K, int CS = 1, bool REREAD = false>
 struct StagedCells {
   static constexpr bool kReread = REREAD;  // the face reads the cells again per group of fields
@@ -295,18 +297,29 @@ void k_sweep_row(SweepParams<NF> p) {
 }
 
 // ---------------------------------------------------------------------------
-// Tile sweep (axis 1 or 2).  A 256-thread workgroup owns TX adjacent x
-// columns of one line along the axis and walks the whole line in chunks of
-// FJ = 256 / TX faces per column.  Each chunk is a row sweep on a strided
+// Tile sweep (any axis).  A 256-thread workgroup owns TX adjacent lines
+// along the axis (x columns for y and z, y rows for x) and walks them whole
+// in chunks of FJ = 256 / TX faces per line.  Each chunk is a row sweep on a
 // tile: its cells are staged in LDS (row r of the chunk at staging indices
 // r TX .. r TX + TX - 1) with their flux, signal speed and Roe inputs, each
 // thread computes one face, the fluxes go through LDS and each thread closes
 // the cell left of its face.  The last face of a chunk is handed to the next
 // chunk through LDS and face 0 of a periodic line is kept for its last cell,
 // so a line of M cells costs M faces (M + 1 when transmissive); only the
-// K - 1 halo rows of each chunk are staged twice.
+// K - 1 halo rows of each chunk are staged twice.  A wavefront's 64 faces
+// form an 8 x 8 patch (8 lines by 8 faces), which a discontinuity crosses
+// far less often than a strip of 64 faces along one line: most wavefronts
+// then skip the limiter (StagedCells with REREAD).
 // ---------------------------------------------------------------------------
-constexpr int kTileColumns = 8;  // x columns per tile-sweep workgroup
+constexpr int kTileColumns = 8;  // columns (lines side by side) per tile-sweep workgroup
+
+// Workgroups of a tile sweep along `axis`: the lines of the other axis times
+// the column groups (x columns for y and z, y rows for x).
+inline long tile_count(int axis, int nx, int ny, int nz) {
+  const long lines = (axis == 2) ? ny : nz;
+  const int across = (axis == 0) ? ny : nx;
+  return lines * ((across + kTileColumns - 1) / kTileColumns);
+}
 
 template <int NF, int K>
 struct SweepTile {
@@ -332,8 +345,9 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
   const int nb = (int)gridDim.x, b = (int)blockIdx.x;
   const int xcd = b & 7, q8 = nb >> 3, r8 = nb & 7;
   const int tile = xcd * q8 + min(xcd, r8) + (b >> 3);
-  const int ncg = (p.nx + TX - 1) / TX;
-  const int o = tile / ncg;  // line of the other axis
+  // column groups: x columns for y and z, y rows for x
+  const int ncg = ((axis == 0 ? p.ny : p.nx) + TX - 1) / TX;
+  const int o = tile / ncg;  // z of an x or y line, y of a z line
   const long N = (long)p.nx * p.ny * p.nz;
   const bool wrap = p.bc == 0;
   const int nface = wrap ? p.n : p.n + 1;  // face j lies between cells j - 1 and j
@@ -346,7 +360,7 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
   // hold registers through the face computation.
   struct Where {
     int col, f;
-    bool xin;
+    bool in;
     Line L;
   };
   auto where = [&]() {
@@ -355,11 +369,16 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
     Where w;
     w.col = t % TX;
     w.f = t / TX;
-    const int x = (tile % ncg) * TX + w.col;
-    w.xin = x < p.nx;
-    const int xs = w.xin ? x : p.nx - 1;  // columns beyond the grid stage a real cell and store nothing
-    w.L = (axis == 1) ? Line{xs + (long)p.nx * p.ny * o, p.nx, p.ny, p.bc}
-                      : Line{xs + (long)p.nx * o, (long)p.nx * p.ny, p.nz, p.bc};
+    const int c = (tile % ncg) * TX + w.col;
+    const int nc = axis == 0 ? p.ny : p.nx;
+    w.in = c < nc;
+    const int cs = w.in ? c : nc - 1;  // columns beyond the grid stage a real line and store nothing
+    if (axis == 0)
+      w.L = Line{((long)cs + (long)p.ny * o) * p.nx, 1, p.nx, p.bc};
+    else if (axis == 1)
+      w.L = Line{cs + (long)p.nx * p.ny * o, p.nx, p.ny, p.bc};
+    else
+      w.L = Line{cs + (long)p.nx * o, (long)p.nx * p.ny, p.nz, p.bc};
     return w;
   };
   for (int k = 0; k < nchunk; ++k) {
@@ -406,7 +425,7 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
       const SweepParams<NF>& pe = *(const SweepParams<NF>*)((const char*)&p + off);
       const Where w = where();
       const int f = w.f, col = w.col, j = j0 + f;
-      const bool act = f < nfk && w.xin;
+      const bool act = f < nfk && w.in;
       if (act && j >= 1) {
         const long cell = w.L.base + (long)(j - 1) * w.L.stride;
         EpiIn<NF> ein;
@@ -686,11 +705,11 @@ hipError_t launch_tile(const SweepLaunch& a) {
   p.inv_dx = a.inv_dx;
   p.fp = a.fp;
   for (int q = 0; q < NF; ++q) p.fld[q] = a.fld[q];
-  if (a.axis != 1 && a.axis != 2) return hipErrorInvalidValue;
-  p.n = (a.axis == 1) ? a.ny : a.nz;
+  if (a.axis < 0 || a.axis > 2) return hipErrorInvalidValue;
+  p.n = (a.axis == 0) ? a.nx : (a.axis == 1) ? a.ny : a.nz;
   p.seg = p.n;
   p.nseg = 1;
-  const long tiles = (long)((a.axis == 1) ? a.nz : a.ny) * ((a.nx + SweepTile<NF, K>::TX - 1) / SweepTile<NF, K>::TX);
+  const long tiles = tile_count(a.axis, a.nx, a.ny, a.nz);
   hipLaunchKernelGGL((k_sweep_tile<NF, K, LIM, ADAPT>), dim3((unsigned)tiles), dim3(256), 0, a.stream, p, a.axis);
   return hipGetLastError();
 }

@@ -268,15 +268,16 @@ int sweep(const tenom_grid* g, int scheme, int limiter, double C_T, double gamma
   L.inv_dx = 1.0 / g->dx[axis];
   const int n_axis = axis == 0 ? d.nx : (axis == 1 ? d.ny : d.nz);
   L.seg = axis == 0 ? 0 : march_segment(n_axis, d.nx, axis == 1 ? d.nz : d.ny);
-  // y and z: the tile sweep walks whole lines, so it is taken when the lines
-  // alone give at least 512 workgroups (two per CU); else the march, which
-  // also splits lines into segments
-  bool tile = false;
-  if (axis != 0) {
-    const long tiles = (long)(axis == 1 ? d.nz : d.ny) * ((d.nx + kTileColumns - 1) / kTileColumns);
-    const int choice = g_sweep_kernel.load(std::memory_order_relaxed);
-    tile = choice == TENOM_SWEEP_TILE || (choice == TENOM_SWEEP_AUTO && tiles >= 512);
-  }
+  // The tile sweep walks whole lines, so it is taken when the lines alone
+  // give at least 512 workgroups (two per CU); else the line kernels: the row
+  // sweep for x (which also splits long rows), the march for y and z (which
+  // splits lines into segments).  Along x the row sweep's contiguous strips
+  // need no halo rows staged twice: at eight points it measured faster than
+  // the tile, at six points slower (256^3 Euler, one box).
+  const long tiles = tile_count(axis, d.nx, d.ny, d.nz);
+  const int choice = g_sweep_kernel.load(std::memory_order_relaxed);
+  const bool tile = choice == TENOM_SWEEP_TILE ||
+                    (choice == TENOM_SWEEP_AUTO && tiles >= 512 && (axis != 0 || K == 6));
   field_map(g, axis, L.fld);
   L.fp = face_params(g, axis, limiter, C_T, gamma);
   L.stream = stream;

@@ -1,17 +1,19 @@
-"""The two kernels of the y and z sweeps against each other and the oracle.
+"""The tile sweep against the line sweeps and the oracle, on every axis.
 
-The tile sweep (a workgroup stages tiles of 8 x columns by a chunk of a
-line in LDS and walks the whole line, handing each chunk's last face to the
-next) and the march sweep (one lane per x column, its stencil in an LDS
-ring) evaluate the same face fluxes and cell updates operation for
-operation, so their results must agree bit for bit.  The shapes put line
-lengths below, at and just above one chunk (32 faces) and several chunks
-with a ragged last one, x extents that leave part of the last column group
-outside the grid, and both boundary rules on every axis; the automatic
-choice takes the march for all of them, so each kernel is forced through
-tenom_set_sweep_kernel.  One case per scheme also goes to the oracle on the
-tile path directly (1e-12 of each field's largest magnitude outside the
-cutoff band, as in the other parity tests).
+The tile sweep (a workgroup stages tiles of 8 adjacent lines by a chunk of
+the line in LDS and walks the lines whole, handing each chunk's last face to
+the next; the lines are x columns for y and z, y rows for x) and the line
+kernels (the row sweep for x; for y and z the march, one lane per x column
+with its stencil in an LDS ring) evaluate the same face fluxes and cell
+updates operation for operation, so their results must agree bit for bit.
+The shapes put line lengths below, at and just above one chunk (32 faces)
+and several chunks with a ragged last one, on every axis, extents across
+the lines that leave part of the last group of 8 outside the grid, and both
+boundary rules on every axis; the automatic choice takes the line kernels
+for all of them, so each kernel is forced through tenom_set_sweep_kernel.
+One case per scheme also goes to the oracle on the tile path directly
+(1e-12 of each field's largest magnitude outside the cutoff band, as in the
+other parity tests).
 """
 import numpy as np
 import pytest
@@ -34,6 +36,9 @@ SHAPES = [
     ("two_chunks_exact", (64, 9, 8), [0, 1, 1], 8 | 0x100, 1, 0.0),
     ("narrow_x", (40, 36, 6), [0, 0, 1], 6, 7, 1e-5),
     ("teno8_long_y", (9, 129, 11), [1, 0, 0], 8, 0, 1e-6),
+    ("x_chunks_ragged", (6, 13, 70), [0, 1, 0], 6, 1, 1e-5),
+    ("x_two_chunks_exact", (8, 17, 64), [1, 0, 0], 8, 1, 1e-7),
+    ("x_chunk_above", (8, 8, 33), [0, 0, 1], 8 | 0x100, 1, 0.0),
 ]
 SHAPE_IDS = [s[0] for s in SHAPES]
 MULTI_D = [c for c in CASES if len(c[1]) >= 2]
@@ -96,7 +101,10 @@ def test_tile_and_march_agree_on_parity_cases(T, case):
     check_identical(T, grid, U, K, lim, C_T, case[0])
 
 
-@pytest.mark.parametrize("spec", [SHAPES[1], SHAPES[4], SHAPES[5]], ids=[SHAPE_IDS[1], SHAPE_IDS[4], SHAPE_IDS[5]])
+ORACLE_SHAPES = [SHAPES[i] for i in (1, 4, 5, 8)]
+
+
+@pytest.mark.parametrize("spec", ORACLE_SHAPES, ids=[s[0] for s in ORACLE_SHAPES])
 def test_tile_against_the_oracle(T, orc, spec):
     grid, U, K, lim, C_T = shape_case(spec, seed=43)
     print(f"[tile vs oracle] {spec[0]}", flush=True)
@@ -114,8 +122,8 @@ def test_tile_against_the_oracle(T, orc, spec):
 
 
 def test_automatic_choice_at_64_cubed_against_the_oracle(T, orc):
-    """At 64^3 the lines of y and z give 512 tile workgroups, so the automatic
-    choice runs the tile sweeps: the divergence of a seeded state against
+    """At 64^3 the lines of every axis give 512 tile workgroups, so the
+    automatic choice runs the tile sweeps: the divergence of a seeded state against
     the oracle over every cell outside the cutoff band (1e-12 of each field's
     largest magnitude)."""
     from parity import band_faces, faces_to_cells
