@@ -240,8 +240,11 @@ __device__ __forceinline__ void teno_m_vjp(const double (&v)[K], const TenoParam
 // Adjoint of one TENO-M reconstruction from its decision code (teno_m with
 // FLAGS): with every decision known the map is linear, so nothing of the
 // forward is recomputed.  All limiters but Van Albada, whose slope function
-// is differentiated at its value (teno_m_vjp_given).
-template <int K, int LIM>
+// is differentiated at its value (teno_m_vjp_given).  With SKIP, a
+// wavefront in which no lane sends a cotangent to the limiter (MP: every
+// candidate passed through; TVD: every candidate smooth) skips the
+// limiter's reverse, which would only add zeros.
+template <int K, int LIM, bool SKIP = false>
 __device__ __forceinline__ void teno_m_vjp_code(uint32_t code, const TenoParams& tp, double rbar,
                                                 double (&vbar)[K]) {
   static_assert(LIM != LIM_VA, "Van Albada needs the values");
@@ -260,6 +263,20 @@ __device__ __forceinline__ void teno_m_vjp_code(uint32_t code, const TenoParams&
 #pragma unroll
     for (int k = 0; k < NK; ++k) cbar[k] = ((code >> k) & 1u) ? T::d(k) * w : 0.0;
   } else if constexpr (LIM == LIM_MP || LIM == LIM_MP_MM) {
+    if constexpr (SKIP) {
+      const bool clipped = ((code >> 8) & ((1u << (2 * NK)) - 1u)) != 0u;
+      if (__builtin_amdgcn_ballot_w64(clipped) == 0) {  // uniform across the wavefront
+#pragma unroll
+        for (int k = 0; k < NK; ++k) cbar[k] = T::d(k) * rbar;
+        T::candidates_vjp(cbar, Dbar);
+#pragma unroll
+        for (int j = 0; j < K - 1; ++j) {
+          vbar[j + 1] += Dbar[j];
+          vbar[j] -= Dbar[j];
+        }
+        return;
+      }
+    }
     double lobar = 0.0, hibar = 0.0;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
@@ -784,7 +801,7 @@ __device__ __forceinline__ double field_fwd(const double* sX, const double* sF, 
   double vp[K], vm[K];
   field_split<NF, K, Q, P>(sX, sF, t, s, vp, vm, W);
   cp = cm = 0u;
-  return 0.5 * (teno_m<K, LIM, true, ADAPT>(vp, tp, cp) + teno_m<K, LIM, true, ADAPT>(vm, tp, cm));
+  return 0.5 * (teno_m<K, LIM, true, ADAPT, true>(vp, tp, cp) + teno_m<K, LIM, true, ADAPT, true>(vm, tp, cm));
 }
 
 // Ordering of LDS accesses between lanes of one wavefront: the hardware
@@ -823,8 +840,8 @@ __device__ __forceinline__ void field_rev(const double* sX, const double* sF, in
     teno_m_vjp_given<K, LIM>(vp, tp, cp, 0.5 * fcbar, vpbar);
     teno_m_vjp_given<K, LIM>(vm, tp, cm, 0.5 * fcbar, vmbar);
   } else {
-    teno_m_vjp_code<K, LIM>(cp, tp, 0.5 * fcbar, vpbar);
-    teno_m_vjp_code<K, LIM>(cm, tp, 0.5 * fcbar, vmbar);
+    teno_m_vjp_code<K, LIM, true>(cp, tp, 0.5 * fcbar, vpbar);
+    teno_m_vjp_code<K, LIM, true>(cm, tp, 0.5 * fcbar, vmbar);
   }
   double g[NF];
   project_row_grad<NF, Q>(s, g);

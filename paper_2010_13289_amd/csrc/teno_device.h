@@ -289,11 +289,14 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
   bool smooth[NK];
   teno_cutoff<K, ADAPT>(D, tp, smooth);
 
-  if constexpr (SKIP && !FLAGS && LIM != LIM_TENO) {
+  if constexpr (SKIP && LIM != LIM_TENO) {
     bool rough = false;
 #pragma unroll
     for (int k = 0; k < NK; ++k) rough |= !smooth[k];
     if (__builtin_amdgcn_ballot_w64(rough) == 0) {  // uniform across the wavefront
+      // codes: every candidate smooth, no limiter decision (none reaches
+      // the result, and the adjoint reads none)
+      if constexpr (FLAGS) bits |= (1u << NK) - 1u;
       double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < NK; ++k) acc = fma(T::d(k), c[k], acc);
