@@ -61,7 +61,10 @@ PEAK_HBM_GBS = 8000.0
 
 # Algorithmic FP64 operations per face vector, itemised in
 # paper_2010_13289_amd/opcount.py (FMA = 2, every other arithmetic, min/max,
-# compare, division or square root = 1) and pinned by tests/test_opcount.py.
+# compare, division or square root = 1) and pinned by tests/test_opcount.py:
+# with every candidate limited (the bound on the method's work) here; the
+# roofline fractions count the limiter where the timed state needs it
+# (limiter_shares).
 FLOPS_PER_FACE_VECTOR = O.face_vector_ops("euler", 3, SCHEME, O.LIM_MP)
 # Algorithmic HBM bytes per cell and step: U^(s) read and U^(s+1) written in
 # every stage, U^n also read in stages 2 and 3 (5 fields x 8 bytes each).
@@ -99,6 +102,19 @@ def kernel_source_digest() -> str:
             with open(os.path.join(d, name), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()
+
+
+def limiter_shares(T, U, grid, scheme, limiter, ct):
+    """Per axis, (rough, nonsmooth) of the reconstructions of state U
+    (opcount.limiter_share) from the smoothness flags of the library's
+    reconstruct_faces (untimed; the flags are the kernels' own decisions)."""
+    nk = (scheme & 0xFF) - 2
+    shares = []
+    for ax in range(grid["ndim"]):
+        _, fl = T.reconstruct_faces(U, grid, scheme, limiter, ct, GAMMA, ax, return_flags=True)
+        shares.append(O.limiter_share(fl, nk))
+        del fl
+    return shares
 
 
 def parse():
@@ -213,7 +229,13 @@ def run_adjoint(args):
     vjp_n, vjp_ms = prof["vjp_axis"]
     faces = 2 * n * n
     vjp_avg_s = vjp_ms / 1e3 / max(vjp_n, 1)
-    vjp_flops = FLOPS_PER_VJP_FACE_VECTOR_2D_K6 * n * n  # one axis: n^2 periodic faces
+    # the limiter counted where the state needs it, averaged over the two
+    # axes (the state is at rest: every stage of the rollout has the same
+    # decisions)
+    shares = limiter_shares(T, U0, grid, scheme, lim, ct)
+    rough = sum(r for r, _ in shares) / len(shares)
+    nonsm = sum(c for _, c in shares) / len(shares)
+    vjp_flops = O.adjoint_face_vector_ops(2, 6, O.LIM_MP, rough=rough, nonsmooth=nonsm) * n * n  # n^2 faces per axis
     return {
         "metric": METRIC,
         "value": 3 * steps * faces / t_bwd,
@@ -243,7 +265,10 @@ def run_adjoint(args):
         "roofline": {"bound": "alu", "kernel": "vjp_axis", "achieved": vjp_flops / vjp_avg_s / 1e12,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": vjp_flops / vjp_avg_s / 1e12 / PEAK_FP64_TFLOPS, "traffic": None,
-                     "avg_launch_ms": vjp_avg_s * 1e3, "flops_per_launch": vjp_flops},
+                     "avg_launch_ms": vjp_avg_s * 1e3, "flops_per_launch": vjp_flops,
+                     "flops_per_launch_every_candidate_limited": FLOPS_PER_VJP_FACE_VECTOR_2D_K6 * n * n},
+        "limiter_share": {ax: {"reconstructions_with_a_nonsmooth_candidate": r,
+                               "nonsmooth_candidates_per_reconstruction": c} for ax, (r, c) in zip("xy", shares)},
         "loss": L_mp,
         "mp_gradient_max_per_field": g_mp.abs().amax(dim=(1, 2)).cpu().tolist(),
         "fd_check_ct0": {"directions": len(rows), "loss": L0,
@@ -329,6 +354,11 @@ def run_batched(args):
     U0 = torch.from_numpy(U_host).to("cuda")
     U = U0.clone()
     scheme, lim, ct = 8, T.LIM_MP, 1e-7
+    # limiter share of the initial state's reconstructions, from the flags of
+    # the problems laid end to end as one transmissive line (untimed; the
+    # 4,095 faces where two problems meet are 0.03 % of the faces)
+    line = dict(ndim=1, n=[int(U_host.shape[1])], dx=[float(np.mean(dx))], bc=[T.BC_TRANSMISSIVE], system=1)
+    (rough, nonsm), = limiter_shares(T, U0, line, scheme, lim, ct)
     best, tile_ms = plan.autotune(U, scheme, lim, ct, GAMMA, CFL, steps=2)
     steps = args.batch_steps
     faces_per_stage = plan.total + plan.count  # n + 1 faces per problem
@@ -360,7 +390,8 @@ def run_batched(args):
     sweep_n, sweep_ms = prof["batch_sweep"]
     dt_n, dt_ms = prof["batch_dt"]
     avg_s = sweep_ms / 1e3 / max(sweep_n, 1)
-    achieved = FLOPS_PER_FACE_VECTOR_1D_K8 * faces_per_stage / avg_s / 1e12
+    flops_launch = O.face_vector_ops("euler", 1, 8, O.LIM_MP, rough=rough, nonsmooth=nonsm) * faces_per_stage
+    achieved = flops_launch / avg_s / 1e12
     sec_per_step = graph_ms / 1e3 / steps
     # one launch per problem: the same kernels with first = p, count = 1
     pp = args.per_problem_steps
@@ -422,7 +453,10 @@ def run_batched(args):
                         else None),
             "traffic_source": TRAFFIC_NOTE,
             "avg_launch_ms": avg_s * 1e3,
-            "flops_per_launch": FLOPS_PER_FACE_VECTOR_1D_K8 * faces_per_stage,
+            "flops_per_launch": flops_launch,
+            "flops_per_launch_every_candidate_limited": FLOPS_PER_FACE_VECTOR_1D_K8 * faces_per_stage,
+            "limiter_share": {"reconstructions_with_a_nonsmooth_candidate": rough,
+                              "nonsmooth_candidates_per_reconstruction": nonsm},
         },
         "graph_wall_ms": (t1 - t0) * 1e3,
         "step_size_kernel_avg_ms": dt_ms / max(dt_n, 1),
@@ -486,6 +520,7 @@ def run_variants(T, U0, grid, n, steps, warmup):
     for name, scheme, lim, ct in VARIANTS:
         U = U0.clone()
         ws = T.Workspace(grid, scheme, U.device)
+        shares = limiter_shares(T, U, grid, scheme, lim, ct)
 
         def step():
             T.rk3_step_cfl(U, grid, scheme, lim, ct, GAMMA, CFL, workspace=ws)
@@ -507,7 +542,9 @@ def run_variants(T, U0, grid, n, steps, warmup):
         ref.setdefault(group, ms)
         sweep_ms = {k: prof[k][1] / max(prof[k][0], 1) for k in ("sweep_x", "sweep_y", "sweep_z")}
         kind = max(sweep_ms, key=sweep_ms.get)  # the slowest sweep of the variant
-        flops_launch = O.face_vector_ops("euler", 3, scheme & 0xFF, lim, bool(scheme & 0x100)) * n ** 3
+        rough, nonsm = shares["xyz".index(kind[-1])]
+        flops_launch = O.face_vector_ops("euler", 3, scheme & 0xFF, lim, bool(scheme & 0x100),
+                                         rough=rough, nonsmooth=nonsm) * n ** 3
         achieved = flops_launch / (sweep_ms[kind] / 1e3) / 1e12
         rows.append({
             "variant": name, "scheme": scheme, "limiter": lim, "C_T": ct, "ms_per_step": ms,
@@ -516,6 +553,8 @@ def run_variants(T, U0, grid, n, steps, warmup):
             "sweep_avg_ms": sweep_ms,
             "roofline": {"bound": "alu", "kernel": kind, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "flops_per_launch": flops_launch},
+            "limiter_share": {ax: {"reconstructions_with_a_nonsmooth_candidate": r,
+                                   "nonsmooth_candidates_per_reconstruction": c} for ax, (r, c) in zip("xyz", shares)},
             "state_finite": T.check_finite(U, grid),
         })
         print(f"# {name}: {ms:.3f} ms/step, {kind} {sweep_ms[kind]:.3f} ms, frac {achieved / PEAK_FP64_TFLOPS:.3f}",
@@ -602,16 +641,8 @@ def main():
     U = U0.clone()
     ws = T.Workspace(grid, SCHEME, dev)
 
-    # fraction of nonsmooth candidate flags on the initial state (untimed)
-    nonsmooth = 0
-    total = 0
-    for ax in range(3):
-        _, fl = T.reconstruct_faces(U, grid, SCHEME, T.LIM_MP, C_T, GAMMA, ax, return_flags=True)
-        bits = fl.to(torch.int32)
-        ones = sum(((bits >> k) & 1).sum().item() for k in range(4))
-        nonsmooth += fl.numel() * 4 - ones
-        total += fl.numel() * 4
-        del fl, bits
+    # limiter share of the initial state's reconstructions, per axis (untimed)
+    shares = limiter_shares(T, U, grid, SCHEME, T.LIM_MP, C_T)
     torch.cuda.synchronize()
 
     if args.calibrate_copy:
@@ -649,7 +680,8 @@ def main():
     kind = max(("sweep_x", "sweep_y", "sweep_z"), key=lambda k: prof[k][1])
     launches, ms = prof[kind]
     avg_s = ms / 1e3 / max(launches, 1)
-    flops_launch = FLOPS_PER_FACE_VECTOR * cells
+    rough, nonsm = shares["xyz".index(kind[-1])]
+    flops_launch = O.face_vector_ops("euler", 3, SCHEME, O.LIM_MP, rough=rough, nonsmooth=nonsm) * cells
     achieved = flops_launch / avg_s / 1e12
     sweeps_ms = {k: (prof[k][1] / max(prof[k][0], 1)) for k in ("sweep_x", "sweep_y", "sweep_z")}
 
@@ -685,11 +717,14 @@ def main():
             "traffic_source": TRAFFIC_NOTE,
             "avg_launch_ms": avg_s * 1e3,
             "flops_per_launch": flops_launch,
+            "flops_per_launch_every_candidate_limited": FLOPS_PER_FACE_VECTOR * cells,
         },
+        "limiter_share": {ax: {"reconstructions_with_a_nonsmooth_candidate": r, "nonsmooth_candidates_per_reconstruction": c}
+                          for ax, (r, c) in zip("xyz", shares)},
         "scalar_reconstructions_per_s": 10 * value,
         "sweep_avg_ms": sweeps_ms,
         "hbm_alg_frac": (BYTES_PER_CELL_STEP * cells / sec_per_step / 1e9) / PEAK_HBM_GBS,
-        "nonsmooth_flag_fraction": nonsmooth / total,
+        "nonsmooth_flag_fraction": sum(c for _, c in shares) / (4 * len(shares)),
         "state_finite": ok,
         "kernel_source_digest": kernel_source_digest(),
     }

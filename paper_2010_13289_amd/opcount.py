@@ -4,9 +4,14 @@ These are the counts the roofline fractions of the benchmark divide by: the
 operations the method as formulated computes per unit of work, not what any
 kernel happens to execute.  Counting rules: add, subtract, multiply,
 divide, square root, abs, min, max and compare count 1; a fused
-multiply-add counts 2; selects, loads and stores count 0.  Where the method
-computes something only for some data (the limiter on nonsmooth
-candidates), every candidate is counted.
+multiply-add counts 2; selects, loads and stores count 0.  The limiter acts
+only on nonsmooth candidates (Eq. mp_flux), so its work depends on the
+data: with rough = nonsmooth = None every candidate is counted (the bound
+on the method's work); given the measured share of the data, its bounds
+(or TVD flux) are counted once per reconstruction with a nonsmooth
+candidate (a fraction `rough` of the reconstructions) and the clamp once
+per nonsmooth candidate (`nonsmooth` per reconstruction on average).  The
+roofline fractions use the measured counts.
 
 Every item is a formula in the structure of the scheme (number of points K,
 candidate stencil widths, fields, dimensions), written next to the step it
@@ -74,10 +79,19 @@ def adaptive_cutoff_ops() -> int:
     return eta + m + g + beta + 1 + 3
 
 
-def reconstruction_items(K: int, limiter: int, adaptive: bool = False) -> dict:
-    """Operations of one scalar TENO-M reconstruction (one side, one field)."""
+def reconstruction_items(K: int, limiter: int, adaptive: bool = False, rough: float | None = None,
+                         nonsmooth: float | None = None) -> dict:
+    """Operations of one scalar TENO-M reconstruction (one side, one field);
+    with rough and nonsmooth the limiter's share as measured (module
+    docstring), else every candidate limited."""
     pts = STENCIL_POINTS[K]
     nk = len(pts)
+    if (rough is None) != (nonsmooth is None):
+        raise ValueError("give both rough and nonsmooth, or neither")
+    if rough is None:
+        rough, nonsmooth = 1, nk
+    elif not (0 <= rough <= 1 and 0 <= nonsmooth <= nk * rough):
+        raise ValueError(f"shares out of range: rough {rough}, nonsmooth {nonsmooth}")
     it = {
         "differences": K - 1,                                   # D_j = v_{j+1} - v_j
         "candidates": sum(linear_form_ops(r - 1) for r in pts),  # Table 1 in differences
@@ -89,14 +103,14 @@ def reconstruction_items(K: int, limiter: int, adaptive: bool = False) -> dict:
     if adaptive:
         it["adaptive_cutoff"] = adaptive_cutoff_ops()
     if limiter in MP_M4 or limiter in MP_MM:
-        it["mp_bounds"] = mp_bounds_ops(limiter)
-        it["medians"] = 2 * nk                                  # clamp of each candidate
+        it["mp_bounds"] = rough * mp_bounds_ops(limiter)
+        it["medians"] = 2 * nonsmooth                           # clamp of each nonsmooth candidate
     elif limiter == LIM_TVD_MINMOD:
-        it["tvd_flux"] = 5 + 1                                  # minmod2, halving
+        it["tvd_flux"] = rough * (5 + 1)                        # minmod2, halving
     elif limiter == LIM_TVD5:
-        it["tvd_flux"] = 8 + 2 + 3 + 3 + 2 + 1                  # B, 2d-, 2d+, two clamps, sign tests, halving
+        it["tvd_flux"] = rough * (8 + 2 + 3 + 3 + 2 + 1)        # B, 2d-, 2d+, two clamps, sign tests, halving
     elif limiter == LIM_VA:
-        it["tvd_flux"] = 3 + 1 + 1 + 3 + 1 + 7                  # d+^2 + d-^2, floor, divide, 2 d+ d- phi, phi/3, flux
+        it["tvd_flux"] = rough * (3 + 1 + 1 + 3 + 1 + 7)        # d+^2 + d-^2, floor, divide, 2 d+ d- phi, phi/3, flux
     elif limiter != LIM_TENO:
         raise ValueError(f"unknown limiter {limiter}")
     if limiter == LIM_TENO:
@@ -106,8 +120,8 @@ def reconstruction_items(K: int, limiter: int, adaptive: bool = False) -> dict:
     return it
 
 
-def reconstruction_ops(K: int, limiter: int, adaptive: bool = False) -> int:
-    return sum(reconstruction_items(K, limiter, adaptive).values())
+def reconstruction_ops(K: int, limiter: int, adaptive: bool = False, rough=None, nonsmooth=None) -> float:
+    return sum(reconstruction_items(K, limiter, adaptive, rough, nonsmooth).values())
 
 
 # --- per face vector ------------------------------------------------------
@@ -152,10 +166,12 @@ def update_ops(nf: int, ndim: int) -> Fraction:
     return 2 * nf + per_cell / ndim
 
 
-def face_vector_items(system: str, ndim: int, K: int, limiter: int, adaptive: bool = False) -> dict:
+def face_vector_items(system: str, ndim: int, K: int, limiter: int, adaptive: bool = False, rough=None,
+                      nonsmooth=None) -> dict:
     """Operations per face vector (all fields, both split sides) of one
-    SSP-RK3 stage sweep: system "euler" or "scalar"."""
-    rec = reconstruction_ops(K, limiter, adaptive)
+    SSP-RK3 stage sweep: system "euler" or "scalar"; rough and nonsmooth
+    as for reconstruction_items."""
+    rec = reconstruction_ops(K, limiter, adaptive, rough, nonsmooth)
     if system == "scalar":
         nf = 1
         it = {"flux_and_split": K * (1 + 3) / K,   # f = a u and the split, once per cell
@@ -178,13 +194,15 @@ def face_vector_items(system: str, ndim: int, K: int, limiter: int, adaptive: bo
     return it
 
 
-def face_vector_ops(system: str, ndim: int, K: int, limiter: int, adaptive: bool = False) -> float:
-    return float(sum(face_vector_items(system, ndim, K, limiter, adaptive).values()))
+def face_vector_ops(system: str, ndim: int, K: int, limiter: int, adaptive: bool = False, rough=None,
+                    nonsmooth=None) -> float:
+    return float(sum(face_vector_items(system, ndim, K, limiter, adaptive, rough, nonsmooth).values()))
 
 
 # --- adjoint (frozen decisions) --------------------------------------------
 
-def adjoint_face_vector_items(ndim: int, K: int, limiter: int, adaptive: bool = False) -> dict:
+def adjoint_face_vector_items(ndim: int, K: int, limiter: int, adaptive: bool = False, rough=None,
+                              nonsmooth=None) -> dict:
     """Operations per Euler face vector of the frozen-branch vector-Jacobian
     product: the forward face evaluated again (its decisions and
     intermediates are needed), then the reverse.  The reverse of a step
@@ -195,9 +213,10 @@ def adjoint_face_vector_items(ndim: int, K: int, limiter: int, adaptive: bool = 
     (indicators, cutoff, limiter choices) have no reverse: with them frozen
     the reconstruction is linear in the split values, and its reverse is
     the transpose of the selected coefficients (differences, candidates,
-    bounds' curvature terms and assembly)."""
-    fwd = face_vector_items("euler", ndim, K, limiter, adaptive)
-    rec = reconstruction_items(K, limiter, adaptive)
+    bounds' curvature terms and assembly); with measured shares the bounds'
+    reverse is counted where the forward's are."""
+    fwd = face_vector_items("euler", ndim, K, limiter, adaptive, rough, nonsmooth)
+    rec = reconstruction_items(K, limiter, adaptive, rough, nonsmooth)
     nf = ndim + 2
     linear_rec = rec["differences"] + rec["candidates"] + rec["assembly"] + rec.get("mp_bounds", 0)
     it = {"forward_" + k: v for k, v in fwd.items()}
@@ -215,8 +234,26 @@ def adjoint_face_vector_items(ndim: int, K: int, limiter: int, adaptive: bool = 
     return it
 
 
-def adjoint_face_vector_ops(ndim: int, K: int, limiter: int, adaptive: bool = False) -> float:
-    return float(sum(adjoint_face_vector_items(ndim, K, limiter, adaptive).values()))
+def adjoint_face_vector_ops(ndim: int, K: int, limiter: int, adaptive: bool = False, rough=None,
+                            nonsmooth=None) -> float:
+    return float(sum(adjoint_face_vector_items(ndim, K, limiter, adaptive, rough, nonsmooth).values()))
+
+
+def limiter_share(flags, nk: int) -> tuple[float, float]:
+    """(rough, nonsmooth) of a set of reconstructions from their smoothness
+    flags (bit k set = candidate k smooth, as the library's
+    reconstruct_faces returns them): the fraction with a nonsmooth
+    candidate and the mean number of nonsmooth candidates.  `flags` is a
+    numpy or torch integer array; every element is one reconstruction."""
+    full = (1 << nk) - 1
+    rough = nonsmooth = 0
+    total = 0
+    for k in range(nk):
+        bad = ((flags >> k) & 1) == 0
+        nonsmooth += int(bad.sum())
+    rough = int(((flags & full) != full).sum())
+    total = int(flags.numel() if hasattr(flags, "numel") else flags.size)
+    return rough / total, nonsmooth / total
 
 
 # --- bytes ---------------------------------------------------------------

@@ -111,3 +111,37 @@ def test_every_variant_has_a_count():
                 assert O.face_vector_ops("euler", 3, K, lim, adaptive) > 0
     with pytest.raises(ValueError):
         O.reconstruction_ops(6, 9)
+
+
+def test_measured_limiter_share():
+    """The limiter counted where the data need it: every candidate nonsmooth
+    gives the full count, none gives the count without the limiter's items,
+    and the count is linear in the shares in between."""
+    for K, lim, nk in ((6, O.LIM_MP, 4), (8, O.LIM_MP, 6), (8, O.LIM_TVD5, 6), (6, O.LIM_VA, 4)):
+        full = O.face_vector_ops("euler", 3, K, lim)
+        assert O.face_vector_ops("euler", 3, K, lim, rough=1.0, nonsmooth=nk) == pytest.approx(full)
+        rec = O.reconstruction_items(K, lim)
+        lim_items = sum(v for k, v in rec.items() if k in ("mp_bounds", "medians", "tvd_flux"))
+        none = O.face_vector_ops("euler", 3, K, lim, rough=0.0, nonsmooth=0.0)
+        assert none == pytest.approx(full - 2 * 5 * lim_items)
+        half = O.face_vector_ops("euler", 3, K, lim, rough=0.5, nonsmooth=nk / 2)
+        assert half == pytest.approx((full + none) / 2)
+    # MP six points: 46 for the bounds and 2 per clamped candidate
+    assert O.reconstruction_ops(6, O.LIM_MP, rough=0.25, nonsmooth=0.5) == pytest.approx(188 - 54 + 0.25 * 46 + 1)
+    assert O.adjoint_face_vector_ops(2, 6, O.LIM_MP, rough=1.0, nonsmooth=4) == pytest.approx(
+        O.adjoint_face_vector_ops(2, 6, O.LIM_MP))
+    with pytest.raises(ValueError):
+        O.reconstruction_ops(6, O.LIM_MP, rough=0.1)
+    with pytest.raises(ValueError):
+        O.reconstruction_ops(6, O.LIM_MP, rough=0.1, nonsmooth=0.5)  # more nonsmooth candidates than 4 x rough
+
+
+def test_limiter_share_from_flags():
+    import numpy as np
+    # four reconstructions of six points: all smooth, one nonsmooth, all nonsmooth, two nonsmooth
+    flags = np.array([0b1111, 0b1110, 0b0000, 0b0101], dtype=np.uint8)
+    rough, nonsmooth = O.limiter_share(flags, 4)
+    assert rough == 0.75
+    assert nonsmooth == (0 + 1 + 4 + 2) / 4
+    # bits above the candidates are ignored
+    assert O.limiter_share(np.array([0xFF, 0xF0], dtype=np.uint8), 4) == (0.5, 2.0)
