@@ -295,7 +295,7 @@ __device__ __forceinline__ double teno_m(const double (&v)[K], const TenoParams&
     for (int k = 0; k < NK; ++k) rough |= !smooth[k];
     if (__builtin_amdgcn_ballot_w64(rough) == 0) {  // uniform across the wavefront
       // codes: every candidate smooth, no limiter decision (none reaches
-      // the result, and the adjoint reads none)
+      // the result, and the adjoint's reverse reads none)
       if constexpr (FLAGS) bits |= (1u << NK) - 1u;
       double acc = 0.0;
 #pragma unroll
