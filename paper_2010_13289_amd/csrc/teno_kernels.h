@@ -352,6 +352,12 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
   const bool wrap = p.bc == 0;
   const int nface = wrap ? p.n : p.n + 1;  // face j lies between cells j - 1 and j
   const int nchunk = (nface + FJ - 1) / FJ;
+  // A periodic x line is walked from its cell 1 (cell m of the walk is cell
+  // m + 1 of the line, the last one cell 0): a chunk then closes 32
+  // consecutive cells that start on a cache-line boundary, and writes them
+  // whole.  On a ring every face has the same stencil either way, so the
+  // fluxes and the results have the same bits.
+  const int rot = (axis == 0 && wrap) ? 1 : 0;
   // Phases of a chunk, each ended by a barrier: staging; faces (their
   // fluxes into LDS); closing the cells, which reads the staged cells and
   // the fluxes from LDS.  No value is held in registers across a barrier.
@@ -388,7 +394,7 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
     {
       const Where w = where();
       for (int r = w.f; r < nfk + K - 1; r += FJ)
-        stage_cell<NF>(stage, NC, r * TX + w.col, p, N, cell_at(w.L, j0 - K / 2 + r));
+        stage_cell<NF>(stage, NC, r * TX + w.col, p, N, cell_at(w.L, j0 - K / 2 + r + rot));
     }
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
@@ -427,7 +433,7 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
       const int f = w.f, col = w.col, j = j0 + f;
       const bool act = f < nfk && w.in;
       if (act && j >= 1) {
-        const long cell = w.L.base + (long)(j - 1) * w.L.stride;
+        const long cell = w.L.base + (long)(j - 1 + rot) * w.L.stride;
         EpiIn<NF> ein;
         epi_load<NF>(pe, N, cell, ein);
         double us[NF], div[NF];
@@ -440,7 +446,7 @@ void k_sweep_tile(SweepParams<NF> p, int axis) {
         epi_store<NF>(pe, N, cell, div, ein, us, epi_dt(pe));
       }
       if (wrap && act && j == nface - 1) {
-        const long cell = w.L.base + (long)j * w.L.stride;
+        const long cell = w.L.base + (long)(rot ? 0 : j) * w.L.stride;
         EpiIn<NF> ein;
         epi_load<NF>(pe, N, cell, ein);
         double us[NF], div[NF];
