@@ -71,6 +71,28 @@ def test_flux_divergence_vjp_matches_reference(T, orc, case):
     assert_close_fields(got, ref, exclude=excl, what=f"{name} VJP")
 
 
+@pytest.mark.parametrize("K, lim, C_T", [(6, 1, 1e-5), (8, 1, 1e-7), (6, 3, 1e-5)], ids=["mp6", "mp8", "tvd5_6"])
+def test_vjp_on_smooth_data_matches_reference(T, orc, K, lim, C_T):
+    """Smooth 2D data, where almost every wavefront's reconstructions have
+    all candidates smooth, so that the reverse skips the limiter's part (it
+    would only add zeros): the VJP against the reference adjoint."""
+    n = 48
+    U, _ = _smooth_state(n)
+    grid = dict(ndim=2, n=[n, n], dx=[1.0 / n, 1.0 / n], bc=[0, 0], system=1)
+    print(f"[vjp smooth] K={K} lim={lim}", flush=True)
+    nk = K - 2
+    for axis in range(2):
+        _, fl = T.reconstruct_faces(to_dev(U), grid, K, lim, C_T, GAMMA, axis, return_flags=True)
+        rough = float(((fl & ((1 << nk) - 1)) != (1 << nk) - 1).double().mean())
+        assert rough < 0.05, f"axis {axis}: {rough:.3f} of the reconstructions have a nonsmooth candidate"
+    Lbar = np.random.default_rng(7).standard_normal(U.shape)
+    ref = RA.flux_divergence_vjp(U, Lbar, grid, K, lim, C_T, GAMMA)
+    got = to_host(T.flux_divergence_vjp(to_dev(U), to_dev(Lbar), grid, K, lim, C_T, GAMMA))
+    excl = band_cells(orc, U, grid, K, lim, C_T, K)
+    assert excl.sum() <= excl.size // 10
+    assert_close_fields(got, ref, exclude=excl, what=f"smooth 2D VJP K={K} lim={lim}")
+
+
 def test_vjp_scale_accumulate_and_determinism(T):
     case = CASES[3]
     name, shape, grid, K, lim, C_T = case
