@@ -721,6 +721,7 @@ def main():
             "avg_launch_ms": avg_s * 1e3,
             "flops_per_launch": flops_launch,
             "flops_per_launch_every_candidate_limited": FLOPS_PER_FACE_VECTOR * cells,
+            "frac_every_candidate_limited": FLOPS_PER_FACE_VECTOR * cells / avg_s / 1e12 / PEAK_FP64_TFLOPS,
         },
         "limiter_share": {ax: {"reconstructions_with_a_nonsmooth_candidate": r, "nonsmooth_candidates_per_reconstruction": c}
                           for ax, (r, c) in zip("xyz", shares)},
