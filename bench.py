@@ -381,6 +381,20 @@ def run_batched(args):
     T.profile_enable(False)
     graph_ms = T.profile_read()["batch_graph"][1]
     ok = bool(torch.isfinite(U).all().item())
+    U_graph = U.clone()
+    # the same steps as one persistent kernel launch (untimed warm-up of one
+    # step, then the timed launch from the same state); the same bits
+    plan.rk3_persistent(U, scheme, lim, ct, GAMMA, CFL, steps=1)
+    U.copy_(U0)
+    plan.reset_times()
+    torch.cuda.synchronize()
+    T.profile_enable(True)
+    plan.rk3_persistent(U, scheme, lim, ct, GAMMA, CFL, steps=steps)
+    torch.cuda.synchronize()
+    T.profile_enable(False)
+    persist_ms = T.profile_read()["batch_persist"][1]
+    persist_same = bool(torch.equal(U, U_graph))
+    del U_graph
     # per-kernel averages from eager steps (kernels inside a graph are not
     # bracketed one by one)
     U.copy_(U0)
@@ -462,6 +476,10 @@ def run_batched(args):
                               "nonsmooth_candidates_per_reconstruction": nonsm},
         },
         "graph_wall_ms": (t1 - t0) * 1e3,
+        "persistent": {"ms_per_step": persist_ms / steps, "launches": 1,
+                       "face_reconstructions_per_s": faces / (persist_ms / 1e3),
+                       "same_bits_as_graph": persist_same,
+                       "note": "all steps of all problems in one kernel launch (tenom_batch_rk3_persistent)"},
         "step_size_kernel_avg_ms": dt_ms / max(dt_n, 1),
         "per_problem_launches": per_problem,
         "state_finite": ok,

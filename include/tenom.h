@@ -353,6 +353,21 @@ int tenom_batch_rk3_graph(tenom_batch_plan* plan, int scheme, int limiter, doubl
                           int steps, double* U, void* stream);
 
 /*
+ * The same `steps` steps of all problems as ONE kernel launch on `stream`
+ * (persistent: each workgroup advances its share of the problems through
+ * every step and stage on its own, with the step sizes and stage states of
+ * tenom_batch_rk3; problems are independent, so no workgroup waits for
+ * another).  The problems are shared out at tenom_batch_create, longest
+ * first, each to the workgroup with the least work so far (three 256-thread
+ * workgroups per compute unit).  Equal in every bit to tenom_batch_rk3 (the
+ * tile shape does not matter); updates the clocks and last steps the same
+ * way.  No allocation, no synchronisation; the launch can be captured in a
+ * HIP graph.
+ */
+int tenom_batch_rk3_persistent(tenom_batch_plan* plan, int scheme, int limiter, double C_T, double gamma, double cfl,
+                               int steps, double* U, void* stream);
+
+/*
  * Autotuner of the tile shape: time `steps` steps (after one untimed step)
  * of every tile on a copy of U, for this scheme and limiter, select the
  * fastest for later calls and return it in *best (nullable).
@@ -407,10 +422,10 @@ int tenom_set_sweep_kernel(int kind);
  * Kinds: 0 face fluxes (reconstruct_faces), 1 x-sweep, 2 y-sweep,
  * 3 z-sweep, 4 batched sweep, 5 batched step size, 6 one replay of a batched
  * graph (kernels inside a graph are not bracketed one by one), 7 one axis of
- * an adjoint (face kernel + gather).  At most 4096 launches are recorded
- * between reads.
+ * an adjoint (face kernel + gather), 8 one persistent batched launch.  At
+ * most 4096 launches are recorded between reads.
  */
-#define TENOM_KERNEL_KINDS 8
+#define TENOM_KERNEL_KINDS 9
 int tenom_profile_enable(int on);
 int tenom_profile_read(int64_t* counts, double* total_ms, int nkinds);
 

@@ -25,7 +25,8 @@ SCHEME_ADAPTIVE = 0x100
 SCHEME_8A = SCHEME_8 | SCHEME_ADAPTIVE   # eight points, adaptive cutoff (TENO8A)
 LIM_TENO, LIM_MP, LIM_TVD_MINMOD, LIM_TVD5, LIM_VA = 0, 1, 2, 3, 4
 LIM_MP_M4_B2, LIM_MP_MM_B4, LIM_MP_MM_B2, LIM_MP_MM_B1 = 5, 6, 7, 8
-KERNEL_KINDS = ("faces", "sweep_x", "sweep_y", "sweep_z", "batch_sweep", "batch_dt", "batch_graph", "vjp_axis")
+KERNEL_KINDS = ("faces", "sweep_x", "sweep_y", "sweep_z", "batch_sweep", "batch_dt", "batch_graph", "vjp_axis",
+                "batch_persist")
 BATCH_TILES = 6
 
 SYMBOLS = (
@@ -34,7 +35,7 @@ SYMBOLS = (
     "tenom_last_error", "tenom_version", "tenom_profile_enable", "tenom_profile_read",
     "tenom_batch_tile_shape", "tenom_batch_create", "tenom_batch_destroy", "tenom_batch_cells",
     "tenom_batch_set_tile", "tenom_batch_get_tile", "tenom_batch_rk3", "tenom_batch_rk3_graph",
-    "tenom_batch_autotune", "tenom_batch_times", "tenom_batch_reset_times",
+    "tenom_batch_autotune", "tenom_batch_times", "tenom_batch_reset_times", "tenom_batch_rk3_persistent",
     "tenom_vjp_workspace_bytes", "tenom_flux_divergence_vjp", "tenom_rk3_vjp_workspace_bytes",
     "tenom_rk3_step_vjp", "tenom_rk3_step_stages", "tenom_rk3_step_vjp_stages", "tenom_rk3_step_cfl",
     "tenom_static_scratch_bytes", "tenom_rk3_step_cfl_noalloc", "tenom_set_sweep_kernel",
@@ -139,6 +140,7 @@ def lib() -> C.CDLL:
         L.tenom_batch_get_tile.argtypes = [vp]
         L.tenom_batch_rk3.argtypes = [vp, ip, ip, dp, dp, dp, ip, ip, ip, vp, vp]
         L.tenom_batch_rk3_graph.argtypes = [vp, ip, ip, dp, dp, dp, ip, vp, vp]
+        L.tenom_batch_rk3_persistent.argtypes = [vp, ip, ip, dp, dp, dp, ip, vp, vp]
         L.tenom_batch_autotune.argtypes = [vp, ip, ip, dp, dp, dp, vp, ip, C.POINTER(C.c_float),
                                            C.POINTER(ip), vp]
         L.tenom_batch_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
@@ -416,6 +418,12 @@ class BatchPlan:
         """`steps` RK3 steps of every problem as one captured-graph launch."""
         _check(lib().tenom_batch_rk3_graph(self._h, scheme, limiter, C_T, gamma, cfl, int(steps),
                                            self._state(U), _stream(stream)))
+        return U
+
+    def rk3_persistent(self, U, scheme, limiter, C_T, gamma, cfl, steps=1, stream=None):
+        """`steps` RK3 steps of every problem in one persistent kernel launch."""
+        _check(lib().tenom_batch_rk3_persistent(self._h, scheme, limiter, C_T, gamma, cfl, int(steps),
+                                                self._state(U), _stream(stream)))
         return U
 
     def autotune(self, U, scheme, limiter, C_T, gamma, cfl, steps=2, stream=None):

@@ -2,8 +2,8 @@
 
 Steps: regenerate csrc/teno_tables.h from gen_tables.py, compile the eight
 forward, the eight tile-sweep and the eight adjoint instantiation units
-(fields x K), the six batched-path units (one per tile shape) and the three
-C-ABI sources in parallel with hipcc, link them into
+(fields x K), the six batched-path units (one per tile shape), the persistent
+batched unit and the three C-ABI sources in parallel with hipcc, link them into
 paper_2010_13289_amd/libtenom.so.
 
     python -m paper_2010_13289_amd.build [--verbose]
@@ -93,6 +93,13 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         objs.append(obj)
         cmds.append([hipcc, *HIPCC_FLAGS, f"-DTENOM_TILE={t}", "-c",
                      os.path.join(CSRC, "tenom_batch_inst.hip"), "-o", obj])
+    obj = os.path.join(BUILD, "batch_persist.o")
+    objs.append(obj)
+    # the persistent kernel loops over problems, steps, stages and segments
+    # around the face: no machine-level loop-invariant code motion, as for the
+    # tile sweeps
+    cmds.append([hipcc, *HIPCC_FLAGS, "-DTENOM_PERSIST", "-mllvm", "-disable-machine-licm", "-c",
+                 os.path.join(CSRC, "tenom_batch_inst.hip"), "-o", obj])
     for src in ("tenom_abi.hip", "tenom_batch.hip", "tenom_noalloc.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         objs.append(obj)

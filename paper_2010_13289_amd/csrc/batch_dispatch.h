@@ -15,3 +15,7 @@ TENOM_DECLARE_BATCH_TILE(2)
 TENOM_DECLARE_BATCH_TILE(3)
 TENOM_DECLARE_BATCH_TILE(4)
 TENOM_DECLARE_BATCH_TILE(5)
+
+// The persistent batched kernel (tenom_batch_inst.hip with -DTENOM_PERSIST):
+// K = 6, K = 8 and the adaptive K = 8 for every limiter.
+hipError_t tenom_batch_persist(int K, int lim, int adapt, const tenom::PersistLaunch& a);

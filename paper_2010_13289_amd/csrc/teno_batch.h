@@ -46,36 +46,49 @@ struct BatchTile {
   static constexpr int CELLS = FACES - 1;
 };
 
+// One segment of one problem, as seen by batch_segment: TPB * FPT faces
+// starting at cell c_begin of the problem (cells base .. base + n - 1 of the
+// state), and the stage update of the segment's cells:
+// Uout = a U0 + b (Us + dt div), U0 read only where a != 0.
+struct SegIn {
+  const double* Us;
+  const double* U0;
+  double* Uout;
+  double a, b, dt, idx;
+  long base, total;
+  int n, c_begin, bc;
+};
+
+// One segment, staged in LDS (at least RowStage<NF>::NE * (TPB * FPT + K - 1)
+// doubles).  Every thread of the workgroup calls it; the staging array is
+// free again when it returns.  `g` may live in LDS: its fields are read where
+// they are used, so that nothing of it is held through the face.
 template <int NF, int K, int LIM, bool ADAPT, int TPB, int FPT>
-__global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
+__device__ __forceinline__ void batch_segment(const SegIn& g, const FaceParams& fp, double* stage) {
   constexpr int SEG = BatchTile<TPB, FPT>::FACES;  // faces per workgroup
   constexpr int NC = SEG + K - 1;                  // staged cells
-  constexpr int NE = RowStage<NF>::NE;
-  __shared__ double stage[NE * NC];
-  const int2 sg = p.segs[blockIdx.x];
-  const int prob = sg.x;
-  const int c_begin = sg.y;
-  const long base = p.off[prob];
-  const int n = (int)(p.off[prob + 1] - base);
-  const bool wrap = (p.bc == 0) && (n <= SEG);  // a whole periodic problem
-  const int ncell = wrap ? n : min(SEG - 1, n - c_begin);
-  const int nface = wrap ? n : ncell + 1;
-  const int nstage = nface + K - 1;
-  const Line L{base, 1, n, p.bc};
   const int t = threadIdx.x;
   __builtin_amdgcn_s_setprio(3);  // high while loads and stores issue, as in the row sweep
-
+  {
+    const int n = g.n, c_begin = g.c_begin;
+    const bool wrap = (g.bc == 0) && (n <= SEG);  // a whole periodic problem
+    const int ncell = wrap ? n : min(SEG - 1, n - c_begin);
+    const int nface = wrap ? n : ncell + 1;
+    const int nstage = nface + K - 1;
+    const Line L{g.base, 1, n, g.bc};
+    const double* Us = g.Us;
+    const long total = g.total;
   for (int c = t; c < nstage; c += TPB) {
     const long cell = cell_at(L, c_begin - K / 2 + c);
     double X[NF];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) X[q] = p.U[q * p.total + cell];
+    for (int q = 0; q < NF; ++q) X[q] = Us[q * total + cell];
 #pragma unroll
     for (int q = 0; q < NF; ++q) stage[q * NC + c] = X[q];
     double F[NF], lam;
     RoeIn<NF> r;
-    cell_physics<NF>(X, p.fp.gamma, F, lam);
-    roe_input<NF>(X, p.fp.gamma, r);
+    cell_physics<NF>(X, fp.gamma, F, lam);
+    roe_input<NF>(X, fp.gamma, r);
 #pragma unroll
     for (int q = 0; q < NF; ++q) stage[(NF + q) * NC + c] = F[q];
     stage[(2 * NF) * NC + c] = lam;
@@ -84,18 +97,26 @@ __global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
     for (int d = 0; d < NF - 2; ++d) stage[(2 * NF + 2 + d) * NC + c] = r.u[d];
     stage[(3 * NF) * NC + c] = r.H;
   }
+  }
   __syncthreads();
   __builtin_amdgcn_s_setprio(0);
 
   double F[FPT][NF];
   double us[FPT][NF];
+  int nface, ncell;
+  {
+    const int n = g.n;
+    const bool wrap = (g.bc == 0) && (n <= SEG);
+    ncell = wrap ? n : min(SEG - 1, n - g.c_begin);
+    nface = wrap ? n : ncell + 1;
+  }
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
     const int j = t + f * TPB;
     if (j < nface) {
       StagedCells<NF, K, 1, true> prov{stage, NC, j};
       uint32_t bits[2][NF];
-      face_flux<NF, K, LIM, ADAPT, false>(prov, p.fp, F[f], bits);
+      face_flux<NF, K, LIM, ADAPT, false>(prov, fp, F[f], bits);
     }
     if (j < ncell) {
 #pragma unroll
@@ -114,22 +135,203 @@ __global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
   }
   __syncthreads();
   __builtin_amdgcn_s_setprio(3);
-  const double dt = p.dt[prob];
-  const double idx = p.inv_dx[prob];
+  {
+    const int n = g.n;
+    const bool wrap = (g.bc == 0) && (n <= SEG);
+    const long base = g.base + g.c_begin, total = g.total;
+    const double a = g.a, b = g.b, dt = g.dt, idx = g.idx;
+    const double* U0 = g.U0;
+    double* Uout = g.Uout;
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
     const int j = t + f * TPB;
     if (j < ncell) {
-      const long cell = base + c_begin + j;
+      const long cell = base + j;
       const int r = (wrap && j == n - 1) ? 0 : j + 1;
 #pragma unroll
       for (int q = 0; q < NF; ++q) {
-        const long o = q * p.total + cell;
+        const long o = q * total + cell;
         const double div = (Fs[q * (SEG + 1) + j] - Fs[q * (SEG + 1) + r]) * idx;
         const double v = fma(dt, div, us[f][q]);
-        p.Uout[o] = (p.a != 0.0) ? fma(p.a, p.U0[o], p.b * v) : p.b * v;
+        Uout[o] = (a != 0.0) ? fma(a, U0[o], b * v) : b * v;
       }
     }
+  }
+  }
+}
+
+template <int NF, int K, int LIM, bool ADAPT, int TPB, int FPT>
+__global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
+  constexpr int NC = BatchTile<TPB, FPT>::FACES + K - 1;
+  __shared__ double stage[RowStage<NF>::NE * NC];
+  const int2 sg = p.segs[blockIdx.x];
+  const int prob = sg.x;
+  SegIn g;
+  g.Us = p.U;
+  g.U0 = p.U0;
+  g.Uout = p.Uout;
+  g.a = p.a;
+  g.b = p.b;
+  g.dt = p.dt[prob];
+  g.idx = p.inv_dx[prob];
+  g.base = p.off[prob];
+  g.n = (int)(p.off[prob + 1] - g.base);
+  g.c_begin = sg.y;
+  g.total = p.total;
+  g.bc = p.bc;
+  batch_segment<NF, K, LIM, ADAPT, TPB, FPT>(g, p.fp, stage);
+}
+
+// Signal rate (|u| + c)/dx of one 1D Euler cell (the CFL condition, Sec. 4).
+__device__ __forceinline__ double euler1d_rate(double rho, double m, double E, double gamma, double inv_dx) {
+  const double ri = 1.0 / rho;
+  const double u = m * ri;
+  const double p = (gamma - 1.0) * (E - 0.5 * rho * (u * u));
+  const double c = sqrt(gamma * p * ri);
+  return (fabs(u) + c) * inv_dx;
+}
+
+// Step size of one problem by one 256-thread workgroup: the largest signal
+// rate over the problem's cells (as an unsigned maximum of the bit
+// patterns, which orders non-negative doubles and puts NaN above all, taken
+// with an LDS atomic: exact and independent of the order) and
+// dt = cfl / rate; every thread returns it.  `m` is one value of shared
+// memory.
+__device__ __forceinline__ double batch_step_size(const double* __restrict__ U, long total, long b, long e,
+                                                  double inv_dx, double gamma, double cfl, unsigned long long* m) {
+  // the thread index through an opaque copy: its addresses are formed here,
+  // not hoisted by the caller's loops and held through the faces
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  asm volatile("" : "+s"(gamma));  // likewise gamma - 1
+  if (t == 0) *m = 0ull;
+  __syncthreads();
+  double best = 0.0;
+  bool nan = false;
+  // four cells' loads in flight per thread (the maximum does not depend on
+  // the order)
+  long i = b + t;
+  for (; i + 768 < e; i += 1024) {
+    double r[4], m[4], E[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      r[k] = U[i + 256 * k];
+      m[k] = U[total + i + 256 * k];
+      E[k] = U[2 * total + i + 256 * k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double s = euler1d_rate(r[k], m[k], E[k], gamma, inv_dx);
+      nan |= (s != s);
+      best = fmax(best, s);
+    }
+  }
+  for (; i < e; i += 256) {
+    const double s = euler1d_rate(U[i], U[total + i], U[2 * total + i], gamma, inv_dx);
+    nan |= (s != s);
+    best = fmax(best, s);
+  }
+  const unsigned long long bits = nan ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(best);
+  atomicMax(m, bits);
+  __syncthreads();
+  const unsigned long long r = *m;
+  __syncthreads();  // m is free again
+  return cfl / __longlong_as_double((long long)r);
+}
+
+// Persistent batched SSP-RK3: one launch runs `steps` steps of every
+// problem.  Workgroup w owns the problems sched_prob[sched_first[w] ..
+// sched_first[w + 1]) (a host-side longest-first assignment by cells) and
+// takes them one after the other: per step the step size, then the three
+// stages, each as the problem's 256-face segments in order, with the
+// problem's stage states in U1, U2 (global memory) and a barrier between
+// stages.  Problems are independent, so no workgroup waits for another.  The faces, step sizes and updates are those of
+// k_batch_dt and k_batch_row: the same bits.
+struct PersistParams {
+  double* U;
+  double* U1;
+  double* U2;
+  long total;
+  const long* off;
+  const double* inv_dx;
+  double* dt;      // [count] last step of each problem
+  double* tclock;  // [count] clock of each problem
+  const int* sched_first;
+  const int* sched_prob;
+  int bc;
+  int steps;
+  double cfl;
+  FaceParams fp;
+};
+
+template <int K, int LIM, bool ADAPT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_batch_persist(PersistParams p) {
+  constexpr int NF = 3, TPB = 256, FPT = 1;
+  constexpr int SEG = BatchTile<TPB, FPT>::FACES;
+  constexpr int NC = SEG + K - 1;
+  __shared__ double stage[RowStage<NF>::NE * NC];
+  __shared__ unsigned long long rate;
+  // The walk over (problem, step, stage, segment) is one loop; its four
+  // counters are the only values carried from pass to pass (the arguments
+  // are read anew in each pass, the segment's description goes through LDS),
+  // so that the face computation holds nothing else in registers.
+  __shared__ SegIn g;
+  int i = p.sched_first[blockIdx.x], step = 0, st = 0, c = 0;
+  for (;;) {
+    long off0 = 0;
+    asm volatile("" : "+s"(off0));
+    const PersistParams& q = *(const PersistParams*)((const char*)&p + off0);
+    if (i >= q.sched_first[blockIdx.x + 1] || q.steps <= 0) break;
+    const int prob = q.sched_prob[i];
+    const long base = q.off[prob];
+    const int n = (int)(q.off[prob + 1] - base);
+    if (st == 0 && c == 0) {  // a step begins: its size, as k_batch_dt
+      const double dt = batch_step_size(q.U, q.total, base, base + n, q.inv_dx[prob], q.fp.gamma, q.cfl, &rate);
+      if (threadIdx.x == 0) {
+        q.dt[prob] = dt;
+        q.tclock[prob] += dt;
+        g.dt = dt;
+      }
+    }
+    if (threadIdx.x == 0) {
+      g.Us = st == 0 ? q.U : (st == 1 ? q.U1 : q.U2);
+      g.U0 = q.U;
+      g.Uout = st == 0 ? q.U1 : (st == 1 ? q.U2 : q.U);
+      g.a = st == 0 ? 0.0 : (st == 1 ? 0.75 : 1.0 / 3.0);
+      g.b = st == 0 ? 1.0 : (st == 1 ? 0.25 : 2.0 / 3.0);
+      g.idx = q.inv_dx[prob];
+      g.base = base;
+      g.total = q.total;
+      g.n = n;
+      g.c_begin = c;
+      g.bc = q.bc;
+    }
+    // the next position: segments of 255 cells, or one wrapped segment for
+    // a periodic problem of at most 256 cells; then the next stage, step,
+    // problem
+    c += ((q.bc == 0) && (n <= SEG)) ? n : SEG - 1;
+    if (c >= n) {
+      c = 0;
+      if (++st == 3) {
+        st = 0;
+        if (++step == q.steps) {
+          step = 0;
+          ++i;
+        }
+      }
+    }
+    __syncthreads();  // g is written
+    // the face's parameters read anew through an opaque pointer to the
+    // argument (held from the kernel's start they would be spilled)
+    long off = 0;
+    asm volatile("" : "+s"(off));
+    const PersistParams& pe = *(const PersistParams*)((const char*)&p + off);
+    batch_segment<NF, K, LIM, ADAPT, TPB, FPT>(g, pe.fp, stage);
+    // the next pass rewrites g and the staging array, and when it begins a
+    // new stage (or step, or problem) it reads what every thread of the
+    // workgroup wrote to global memory in this stage: the barrier's
+    // workgroup-scope fences order both (the workgroup runs on one CU)
+    __syncthreads();
   }
 }
 
@@ -166,6 +368,19 @@ hipError_t launch_batch_row(const BatchLaunch& a) {
   p.bc = a.bc;
   p.fp = a.fp;
   hipLaunchKernelGGL((k_batch_row<3, K, LIM, ADAPT, TPB, FPT>), dim3(a.nseg), dim3(TPB), 0, a.stream, p);
+  return hipGetLastError();
+}
+
+struct PersistLaunch {
+  PersistParams p;
+  int nblk;
+  hipStream_t stream;
+};
+
+template <int K, int LIM, bool ADAPT>
+hipError_t launch_batch_persist(const PersistLaunch& a) {
+  if (a.nblk <= 0 || a.p.steps <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_batch_persist<K, LIM, ADAPT>), dim3(a.nblk), dim3(256), 0, a.stream, a.p);
   return hipGetLastError();
 }
 

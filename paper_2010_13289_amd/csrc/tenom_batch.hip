@@ -7,7 +7,10 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <queue>
+#include <utility>
 #include <vector>
 
 #include "../../include/tenom.h"
@@ -35,6 +38,11 @@ struct tenom_batch_plan {
     std::vector<int> first;  // [count + 1] first segment of each problem
   } tiling[kNumTiles];
   int tile = 3;
+  // persistent path: workgroup w takes problems sched_prob[sched_first[w] ..
+  // sched_first[w + 1])
+  int nblk = 0;
+  int* sched_first_d = nullptr;
+  int* sched_prob_d = nullptr;
   hipStream_t cap = nullptr;  // capture stream of the graph path
   hipGraphExec_t exec = nullptr;
   struct Key {
@@ -51,15 +59,6 @@ struct tenom_batch_plan {
 
 namespace {
 
-// Signal rate (|u| + c)/dx of one 1D Euler cell.
-__device__ __forceinline__ double euler1d_rate(double rho, double m, double E, double gamma, double inv_dx) {
-  const double ri = 1.0 / rho;
-  const double u = m * ri;
-  const double p = (gamma - 1.0) * (E - 0.5 * rho * (u * u));
-  const double c = sqrt(gamma * p * ri);
-  return (fabs(u) + c) * inv_dx;
-}
-
 // Step sizes: one workgroup of 256 threads per problem p0 + blockIdx.x
 // computes the largest signal rate (|u| + c)/dx over the problem's cells,
 // its step dt = cfl / rate and the problem's clock t += dt.
@@ -68,29 +67,9 @@ __global__ __launch_bounds__(256) void k_batch_dt(const double* __restrict__ U, 
                                                   double gamma, double cfl, int p0, double* __restrict__ dt,
                                                   double* __restrict__ tclock) {
   const int prob = p0 + blockIdx.x;
-  const long b = off[prob], e = off[prob + 1];
-  const double ix = inv_dx[prob];
-  double best = 0.0;
-  bool nan = false;
-  for (long i = b + threadIdx.x; i < e; i += 256) {
-    const double s = euler1d_rate(U[i], U[total + i], U[2 * total + i], gamma, ix);
-    nan |= (s != s);
-    best = fmax(best, s);
-  }
-  // non-negative doubles order like their bit patterns; NaN above all
-  unsigned long long bits = nan ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(best);
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long v = __shfl_down(bits, o, 64);
-    bits = v > bits ? v : bits;
-  }
-  __shared__ unsigned long long part[4];
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = bits;
-  __syncthreads();
+  __shared__ unsigned long long rate;
+  const double d = batch_step_size(U, total, off[prob], off[prob + 1], inv_dx[prob], gamma, cfl, &rate);
   if (threadIdx.x == 0) {
-    unsigned long long m = part[0];
-    for (int w = 1; w < 4; ++w) m = part[w] > m ? part[w] : m;
-    const double rate = __longlong_as_double((long long)m);
-    const double d = cfl / rate;
     dt[prob] = d;
     tclock[prob] += d;
   }
@@ -120,12 +99,44 @@ void build_segments(const std::vector<long>& off, int bc, int faces, std::vector
   first[count] = (int)segs.size();
 }
 
+// Problems of the persistent path per workgroup: longest first, each to the
+// workgroup with the least work so far (cells plus a fixed cost per problem
+// for its step size and segment barriers); a workgroup takes its problems
+// in that order.
+void build_schedule(const std::vector<long>& off, int nblk, std::vector<int>& first, std::vector<int>& prob) {
+  const int count = (int)off.size() - 1;
+  std::vector<int> order(count);
+  for (int p = 0; p < count; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+  using Bin = std::pair<long, int>;  // (work, workgroup)
+  std::priority_queue<Bin, std::vector<Bin>, std::greater<Bin>> bins;
+  for (int w = 0; w < nblk; ++w) bins.push({0, w});
+  std::vector<std::vector<int>> lists(nblk);
+  for (int p : order) {
+    Bin b = bins.top();
+    bins.pop();
+    lists[b.second].push_back(p);
+    b.first += (off[p + 1] - off[p]) + 256;
+    bins.push(b);
+  }
+  first.assign(nblk + 1, 0);
+  prob.clear();
+  for (int w = 0; w < nblk; ++w) {
+    first[w] = (int)prob.size();
+    prob.insert(prob.end(), lists[w].begin(), lists[w].end());
+  }
+  first[nblk] = (int)prob.size();
+}
+
 void release(tenom_batch_plan* P) {
   if (!P) return;
   if (P->exec) hipGraphExecDestroy(P->exec);
   if (P->cap) hipStreamDestroy(P->cap);
   for (auto& T : P->tiling)
     if (T.segs_d) hipFree(T.segs_d);
+  hipFree(P->sched_first_d);
+  hipFree(P->sched_prob_d);
   hipFree(P->off_d);
   hipFree(P->inv_dx_d);
   hipFree(P->dt_d);
@@ -261,6 +272,21 @@ int tenom_batch_create(int count, const int64_t* n, const double* dx, int bc, te
       if (e == hipSuccess) e = hipMemcpy(P->tiling[t].segs_d, segs.data(), segs.size() * sizeof(int2), hipMemcpyHostToDevice);
     }
   }
+  if (e == hipSuccess && count > 0) {
+    // three 256-thread workgroups per compute unit (the persistent kernel's
+    // occupancy), at most one per problem
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
+    if (e == hipSuccess) {
+      P->nblk = std::min(count, std::max(1, 3 * cus));
+      std::vector<int> first, prob;
+      build_schedule(off, P->nblk, first, prob);
+      e = hipMalloc(&P->sched_first_d, first.size() * sizeof(int));
+      if (e == hipSuccess) e = hipMalloc(&P->sched_prob_d, prob.size() * sizeof(int));
+      if (e == hipSuccess) e = hipMemcpy(P->sched_first_d, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(P->sched_prob_d, prob.data(), prob.size() * sizeof(int), hipMemcpyHostToDevice);
+    }
+  }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
     release(P);
@@ -345,6 +371,38 @@ int tenom_batch_rk3_graph(tenom_batch_plan* plan, int scheme, int limiter, doubl
     e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
   }
   return e == hipSuccess ? TENOM_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+int tenom_batch_rk3_persistent(tenom_batch_plan* plan, int scheme, int limiter, double C_T, double gamma, double cfl,
+                               int steps, double* U, void* stream) {
+  g_err[0] = 0;
+  Method m;
+  int rc = check_call(plan, scheme, limiter, C_T, gamma, cfl, steps, U, &m);
+  if (rc) return rc;
+  if (plan->count == 0 || steps == 0) return TENOM_OK;
+  PersistLaunch L;
+  L.p.U = U;
+  L.p.U1 = plan->U1;
+  L.p.U2 = plan->U2;
+  L.p.total = plan->total;
+  L.p.off = plan->off_d;
+  L.p.inv_dx = plan->inv_dx_d;
+  L.p.dt = plan->dt_d;
+  L.p.tclock = plan->t_d;
+  L.p.sched_first = plan->sched_first_d;
+  L.p.sched_prob = plan->sched_prob_d;
+  L.p.bc = plan->bc;
+  L.p.steps = steps;
+  L.p.cfl = cfl;
+  L.p.fp = m.fp;
+  L.nblk = plan->nblk;
+  L.stream = (hipStream_t)stream;
+  hipError_t e;
+  {
+    ProfScope ps(8, L.stream);
+    e = tenom_batch_persist(m.K, m.kind, m.adapt ? 1 : 0, L);
+  }
+  return e == hipSuccess ? TENOM_OK : hip_fail(e, "persistent batched launch");
 }
 
 int tenom_batch_autotune(tenom_batch_plan* plan, int scheme, int limiter, double C_T, double gamma, double cfl,

@@ -1,8 +1,8 @@
 """GPU parity of the batched path (many independent 1D Euler problems of
 uneven size, tenom_batch_*) against the oracle run problem by problem, and
-its invariants: every tile shape, the graph replay and per-problem launches
-give the same bits; the autotuner leaves the state alone; an empty batch is
-a no-op."""
+its invariants: every tile shape, the graph replay, the persistent launch
+and per-problem launches give the same bits; the autotuner leaves the state
+alone; an empty batch is a no-op."""
 import numpy as np
 import pytest
 
@@ -139,6 +139,28 @@ def test_graph_replays_match_eager_steps(T):
     plan.close()
 
 
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_persistent_launch_matches_eager_steps(T, case):
+    """One persistent launch of 5 steps equals 5 eager steps in every bit,
+    with the same clocks and last steps (wrapped periodic problems of at
+    most 256 cells, multi-segment problems, both boundary rules)."""
+    name, scheme, lim, C_T, bc = case
+    U, dx, _ = ragged_batch(SIZES, seed0=21)
+    eager = T.BatchPlan(SIZES, dx, bc)
+    pers = T.BatchPlan(SIZES, dx, bc)
+    A = to_dev(U)
+    B = to_dev(U)
+    print(f"[batch persistent] {name}", flush=True)
+    eager.rk3(A, scheme, lim, C_T, GAMMA, CFL, steps=5)
+    pers.rk3_persistent(B, scheme, lim, C_T, GAMMA, CFL, steps=5)
+    assert np.array_equal(to_host(A), to_host(B)), f"{name}: state differs"
+    ta, da = eager.times()
+    tb, db = pers.times()
+    assert np.array_equal(ta, tb) and np.array_equal(da, db), f"{name}: clocks differ"
+    eager.close()
+    pers.close()
+
+
 def test_problem_ranges_match_the_whole_batch(T):
     """One launch per problem (first = p, count = 1) gives the same bits and
     clocks as one launch over the batch."""
@@ -187,6 +209,7 @@ def test_empty_batch_and_errors(T):
     U = torch.empty((3, 0), dtype=torch.float64, device="cuda")
     plan.rk3(U, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=5)
     plan.rk3_graph(U, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=5)
+    plan.rk3_persistent(U, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=5)
     assert plan.autotune(U, 8, T.LIM_MP, 1e-7, GAMMA, CFL)[0] == plan.tile
     assert plan.times()[0].size == 0
     plan.close()
@@ -229,6 +252,15 @@ def test_batched_4096_problems_graph_100_steps(T, orc):
     torch.cuda.synchronize()
     t, _ = plan.times()
     Ug = to_host(Ud)
+    # the persistent launch: the same 100 steps in one kernel, the same bits
+    pers = T.BatchPlan(sizes, dx, 1)
+    Up = to_dev(U)
+    print("[batch 4096] persistent launch, 100 steps", flush=True)
+    pers.rk3_persistent(Up, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=100)
+    assert np.array_equal(to_host(Up), Ug), "persistent launch differs from the graph"
+    assert np.array_equal(pers.times()[0], t)
+    pers.close()
+    del Up
     assert np.all(np.isfinite(Ug)) and np.all(Ug[0] > 0)
     rho, m, E = Ug
     assert np.all(E - 0.5 * m * m / rho > 0)
