@@ -212,7 +212,7 @@ int comb3(double* out, double c0, const double* x, double c1, const double* y1, 
   return e == hipSuccess ? TENOM_OK : hip_fail(e, "combination launch");
 }
 
-// kernel of the y and z sweeps (tenom_set_sweep_kernel)
+// kernel of the sweeps (tenom_set_sweep_kernel)
 std::atomic<int> g_sweep_kernel{TENOM_SWEEP_AUTO};
 
 int march_segment(int n, int nx, int n_other) {
