@@ -357,9 +357,10 @@ int tenom_batch_rk3_graph(tenom_batch_plan* plan, int scheme, int limiter, doubl
  * (persistent: each workgroup advances its share of the problems through
  * every step and stage on its own, with the step sizes and stage states of
  * tenom_batch_rk3; problems are independent, so no workgroup waits for
- * another).  The problems are shared out at tenom_batch_create, longest
- * first, each to the workgroup with the least work so far (three 256-thread
- * workgroups per compute unit).  Equal in every bit to tenom_batch_rk3 (the
+ * another).  Three 256-thread workgroups per compute unit take the problems
+ * from a queue in the plan, longest first, each whole; the plan's queue is
+ * clear again when the launch ends, so launches on one plan must not
+ * overlap (calls on a plan never may).  Equal in every bit to tenom_batch_rk3 (the
  * tile shape does not matter); updates the clocks and last steps the same
  * way.  No allocation, no synchronisation; the launch can be captured in a
  * HIP graph.

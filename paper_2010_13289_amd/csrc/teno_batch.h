@@ -240,12 +240,13 @@ __device__ __forceinline__ double batch_step_size(const double* __restrict__ U, 
 }
 
 // Persistent batched SSP-RK3: one launch runs `steps` steps of every
-// problem.  Workgroup w owns the problems sched_prob[sched_first[w] ..
-// sched_first[w + 1]) (a host-side longest-first assignment by cells) and
-// takes them one after the other: per step the step size, then the three
-// stages, each as the problem's 256-face segments in order, with the
+// problem.  Each workgroup takes the next problem of `order` (longest first)
+// from a queue counter, and runs it whole: per step the step size, then the
+// three stages, each as the problem's 256-face segments in order, with the
 // problem's stage states in U1, U2 (global memory) and a barrier between
-// stages.  Problems are independent, so no workgroup waits for another.  The faces, step sizes and updates are those of
+// stages; then it takes the next.  Problems are independent, so no workgroup
+// waits for another.  The last workgroup to finish clears the queue for the
+// next launch.  The faces, step sizes and updates are those of
 // k_batch_dt and k_batch_row: the same bits.
 struct PersistParams {
   double* U;
@@ -256,8 +257,9 @@ struct PersistParams {
   const double* inv_dx;
   double* dt;      // [count] last step of each problem
   double* tclock;  // [count] clock of each problem
-  const int* sched_first;
-  const int* sched_prob;
+  const int* order;         // [count] problems, longest first
+  unsigned* queue;          // [2] next index of order, workgroups finished (0 between launches)
+  int count;
   int bc;
   int steps;
   double cfl;
@@ -276,13 +278,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   // are read anew in each pass, the segment's description goes through LDS),
   // so that the face computation holds nothing else in registers.
   __shared__ SegIn g;
-  int i = p.sched_first[blockIdx.x], step = 0, st = 0, c = 0;
+  __shared__ int next;
+  if (threadIdx.x == 0) next = (int)atomicAdd(p.queue, 1u);
+  __syncthreads();
+  int i = next, step = 0, st = 0, c = 0;
   for (;;) {
     long off0 = 0;
     asm volatile("" : "+s"(off0));
     const PersistParams& q = *(const PersistParams*)((const char*)&p + off0);
-    if (i >= q.sched_first[blockIdx.x + 1] || q.steps <= 0) break;
-    const int prob = q.sched_prob[i];
+    if (i >= q.count || q.steps <= 0) break;
+    const int prob = q.order[i];
     const long base = q.off[prob];
     const int n = (int)(q.off[prob + 1] - base);
     if (st == 0 && c == 0) {  // a step begins: its size, as k_batch_dt
@@ -309,6 +314,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     // the next position: segments of 255 cells, or one wrapped segment for
     // a periodic problem of at most 256 cells; then the next stage, step,
     // problem
+    bool done = false;  // the problem's last segment
     c += ((q.bc == 0) && (n <= SEG)) ? n : SEG - 1;
     if (c >= n) {
       c = 0;
@@ -316,7 +322,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         st = 0;
         if (++step == q.steps) {
           step = 0;
-          ++i;
+          done = true;
         }
       }
     }
@@ -327,11 +333,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     asm volatile("" : "+s"(off));
     const PersistParams& pe = *(const PersistParams*)((const char*)&p + off);
     batch_segment<NF, K, LIM, ADAPT, TPB, FPT>(g, pe.fp, stage);
+    if (done && threadIdx.x == 0) next = (int)atomicAdd(pe.queue, 1u);
     // the next pass rewrites g and the staging array, and when it begins a
     // new stage (or step, or problem) it reads what every thread of the
     // workgroup wrote to global memory in this stage: the barrier's
     // workgroup-scope fences order both (the workgroup runs on one CU)
     __syncthreads();
+    if (done) i = next;
+  }
+  // every workgroup has taken its last index once it counts itself finished:
+  // the last one clears the queue
+  if (threadIdx.x == 0) {
+    long off = 0;
+    asm volatile("" : "+s"(off));
+    const PersistParams& pe = *(const PersistParams*)((const char*)&p + off);
+    if (atomicAdd(pe.queue + 1, 1u) == gridDim.x - 1) {
+      atomicExch(pe.queue, 0u);
+      atomicExch(pe.queue + 1, 0u);
+    }
   }
 }
 

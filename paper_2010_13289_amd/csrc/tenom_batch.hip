@@ -9,8 +9,6 @@
 
 #include <algorithm>
 #include <new>
-#include <queue>
-#include <utility>
 #include <vector>
 
 #include "../../include/tenom.h"
@@ -38,11 +36,10 @@ struct tenom_batch_plan {
     std::vector<int> first;  // [count + 1] first segment of each problem
   } tiling[kNumTiles];
   int tile = 3;
-  // persistent path: workgroup w takes problems sched_prob[sched_first[w] ..
-  // sched_first[w + 1])
+  // persistent path: the problems longest first, and the queue counters
   int nblk = 0;
-  int* sched_first_d = nullptr;
-  int* sched_prob_d = nullptr;
+  int* order_d = nullptr;
+  unsigned* queue_d = nullptr;
   hipStream_t cap = nullptr;  // capture stream of the graph path
   hipGraphExec_t exec = nullptr;
   struct Key {
@@ -99,34 +96,14 @@ void build_segments(const std::vector<long>& off, int bc, int faces, std::vector
   first[count] = (int)segs.size();
 }
 
-// Problems of the persistent path per workgroup: longest first, each to the
-// workgroup with the least work so far (cells plus a fixed cost per problem
-// for its step size and segment barriers); a workgroup takes its problems
-// in that order.
-void build_schedule(const std::vector<long>& off, int nblk, std::vector<int>& first, std::vector<int>& prob) {
+// Problems of the persistent path, longest first (ties by index).
+std::vector<int> longest_first(const std::vector<long>& off) {
   const int count = (int)off.size() - 1;
   std::vector<int> order(count);
   for (int p = 0; p < count; ++p) order[p] = p;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
-  using Bin = std::pair<long, int>;  // (work, workgroup)
-  std::priority_queue<Bin, std::vector<Bin>, std::greater<Bin>> bins;
-  for (int w = 0; w < nblk; ++w) bins.push({0, w});
-  std::vector<std::vector<int>> lists(nblk);
-  for (int p : order) {
-    Bin b = bins.top();
-    bins.pop();
-    lists[b.second].push_back(p);
-    b.first += (off[p + 1] - off[p]) + 256;
-    bins.push(b);
-  }
-  first.assign(nblk + 1, 0);
-  prob.clear();
-  for (int w = 0; w < nblk; ++w) {
-    first[w] = (int)prob.size();
-    prob.insert(prob.end(), lists[w].begin(), lists[w].end());
-  }
-  first[nblk] = (int)prob.size();
+  return order;
 }
 
 void release(tenom_batch_plan* P) {
@@ -135,8 +112,8 @@ void release(tenom_batch_plan* P) {
   if (P->cap) hipStreamDestroy(P->cap);
   for (auto& T : P->tiling)
     if (T.segs_d) hipFree(T.segs_d);
-  hipFree(P->sched_first_d);
-  hipFree(P->sched_prob_d);
+  hipFree(P->order_d);
+  hipFree(P->queue_d);
   hipFree(P->off_d);
   hipFree(P->inv_dx_d);
   hipFree(P->dt_d);
@@ -279,12 +256,11 @@ int tenom_batch_create(int count, const int64_t* n, const double* dx, int bc, te
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device);
     if (e == hipSuccess) {
       P->nblk = std::min(count, std::max(1, 3 * cus));
-      std::vector<int> first, prob;
-      build_schedule(off, P->nblk, first, prob);
-      e = hipMalloc(&P->sched_first_d, first.size() * sizeof(int));
-      if (e == hipSuccess) e = hipMalloc(&P->sched_prob_d, prob.size() * sizeof(int));
-      if (e == hipSuccess) e = hipMemcpy(P->sched_first_d, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice);
-      if (e == hipSuccess) e = hipMemcpy(P->sched_prob_d, prob.data(), prob.size() * sizeof(int), hipMemcpyHostToDevice);
+      const std::vector<int> order = longest_first(off);
+      e = hipMalloc(&P->order_d, order.size() * sizeof(int));
+      if (e == hipSuccess) e = hipMalloc(&P->queue_d, 2 * sizeof(unsigned));
+      if (e == hipSuccess) e = hipMemcpy(P->order_d, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemset(P->queue_d, 0, 2 * sizeof(unsigned));
     }
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking);
@@ -389,8 +365,9 @@ int tenom_batch_rk3_persistent(tenom_batch_plan* plan, int scheme, int limiter, 
   L.p.inv_dx = plan->inv_dx_d;
   L.p.dt = plan->dt_d;
   L.p.tclock = plan->t_d;
-  L.p.sched_first = plan->sched_first_d;
-  L.p.sched_prob = plan->sched_prob_d;
+  L.p.order = plan->order_d;
+  L.p.queue = plan->queue_d;
+  L.p.count = plan->count;
   L.p.bc = plan->bc;
   L.p.steps = steps;
   L.p.cfl = cfl;
