@@ -278,8 +278,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   // are read anew in each pass, the segment's description goes through LDS),
   // so that the face computation holds nothing else in registers.
   __shared__ SegIn g;
-  __shared__ int next;
-  if (threadIdx.x == 0) next = (int)atomicAdd(p.queue, 1u);
+  // the current problem, loaded once when a workgroup takes it
+  __shared__ int next, cur_n;
+  __shared__ long cur_base;
+  __shared__ double cur_idx;
+  auto take = [&](const PersistParams& q) {  // thread 0
+    next = (int)atomicAdd(q.queue, 1u);
+    if (next < q.count) {
+      const int prob = q.order[next];
+      cur_base = q.off[prob];
+      cur_n = (int)(q.off[prob + 1] - cur_base);
+      cur_idx = q.inv_dx[prob];
+    }
+  };
+  if (threadIdx.x == 0) take(p);
   __syncthreads();
   int i = next, step = 0, st = 0, c = 0;
   for (;;) {
@@ -287,12 +299,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     asm volatile("" : "+s"(off0));
     const PersistParams& q = *(const PersistParams*)((const char*)&p + off0);
     if (i >= q.count || q.steps <= 0) break;
-    const int prob = q.order[i];
-    const long base = q.off[prob];
-    const int n = (int)(q.off[prob + 1] - base);
+    const long base = cur_base;
+    const int n = cur_n;
     if (st == 0 && c == 0) {  // a step begins: its size, as k_batch_dt
-      const double dt = batch_step_size(q.U, q.total, base, base + n, q.inv_dx[prob], q.fp.gamma, q.cfl, &rate);
+      const double dt = batch_step_size(q.U, q.total, base, base + n, cur_idx, q.fp.gamma, q.cfl, &rate);
       if (threadIdx.x == 0) {
+        const int prob = q.order[i];
         q.dt[prob] = dt;
         q.tclock[prob] += dt;
         g.dt = dt;
@@ -304,7 +316,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       g.Uout = st == 0 ? q.U1 : (st == 1 ? q.U2 : q.U);
       g.a = st == 0 ? 0.0 : (st == 1 ? 0.75 : 1.0 / 3.0);
       g.b = st == 0 ? 1.0 : (st == 1 ? 0.25 : 2.0 / 3.0);
-      g.idx = q.inv_dx[prob];
+      g.idx = cur_idx;
       g.base = base;
       g.total = q.total;
       g.n = n;
@@ -333,7 +345,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     asm volatile("" : "+s"(off));
     const PersistParams& pe = *(const PersistParams*)((const char*)&p + off);
     batch_segment<NF, K, LIM, ADAPT, TPB, FPT>(g, pe.fp, stage);
-    if (done && threadIdx.x == 0) next = (int)atomicAdd(pe.queue, 1u);
+    if (done && threadIdx.x == 0) take(pe);
     // the next pass rewrites g and the staging array, and when it begins a
     // new stage (or step, or problem) it reads what every thread of the
     // workgroup wrote to global memory in this stage: the barrier's
