@@ -161,6 +161,36 @@ def test_persistent_launch_matches_eager_steps(T, case):
     pers.close()
 
 
+def test_persistent_launch_in_a_captured_graph(T):
+    """The persistent launch captured in a graph and replayed three times,
+    with other device work between the replays, equals the eager launch in
+    every bit each time (the plan's queue is clear again after each launch)."""
+    import torch
+    U, dx, _ = ragged_batch(SIZES, seed0=27)
+    plan = T.BatchPlan(SIZES, dx, 1)
+    ref_plan = T.BatchPlan(SIZES, dx, 1)
+    Us = to_dev(U)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            plan.rk3_persistent(Us, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=2)
+    torch.cuda.current_stream().wait_stream(side)
+    R = to_dev(U)
+    for replay in range(3):
+        print(f"[batch persistent graph] replay {replay}", flush=True)
+        Us.copy_(to_dev(U) if replay == 0 else Us)
+        g.replay()
+        ref_plan.rk3_persistent(R, 8, T.LIM_MP, 1e-7, GAMMA, CFL, steps=2)
+        torch.cuda.synchronize()
+        assert torch.equal(Us, R), f"replay {replay} differs"
+        R.mul_(1.0)  # unrelated work between replays
+        torch.cuda.synchronize()
+    plan.close()
+    ref_plan.close()
+
+
 def test_problem_ranges_match_the_whole_batch(T):
     """One launch per problem (first = p, count = 1) gives the same bits and
     clocks as one launch over the batch."""
