@@ -1009,19 +1009,9 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   const int tid = q * FW + f;
   const int half = f >> 6, lane = f & 63;
 
-  // field 1's thread f finishes owned cell c0 + f (step 5); the cell's src
-  // values of the output rule are loaded first so that the loads' latency
-  // hides behind the kernel instead of ending it
+  // field 1's thread f finishes owned cell c0 + f (step 5)
   const bool cell_thread = (q == 1 && f < ncell);
   __builtin_amdgcn_s_setprio(3);  // high while loads and stores issue (entry, staging, the write)
-  double prev[NF];
-#pragma unroll
-  for (int r = 0; r < NF; ++r) prev[r] = 0.0;
-  if (vo.src && cell_thread) {
-    const long cell = L.base + (long)(c0 + f) * L.stride;
-#pragma unroll
-    for (int r = 0; r < NF; ++r) prev[r] = vo.src[(long)fld[r] * N + cell];
-  }
 
   // 1. staging; accumulators and the constants' cotangents cleared
   for (int i = tid; i < npos; i += FW * NF) {
@@ -1171,6 +1161,17 @@ __global__ __launch_bounds__(64 * NF) __attribute__((amdgpu_waves_per_eu(VjpOccu
   const int lo = (!per && c == 0) ? i - H : i;
   const int hi = (!per && c == n - 1) ? i + H : i;
   double xs[NF];
+  // the cell's src values of the output rule, loaded before the slot sums so
+  // that their latency hides behind them (loaded at the kernel's entry they
+  // held registers through the face and pushed values into scratch)
+  double prev[NF];
+#pragma unroll
+  for (int r = 0; r < NF; ++r) prev[r] = 0.0;
+  if (vo.src && cell_thread) {
+    const long cell = L.base + (long)(c0 + f) * L.stride;
+#pragma unroll
+    for (int r = 0; r < NF; ++r) prev[r] = vo.src[(long)fld[r] * N + cell];
+  }
   if (cell_thread) {
     double fs[NF], ls = 0.0, X[NF];
 #pragma unroll
