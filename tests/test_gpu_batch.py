@@ -102,6 +102,40 @@ def test_batch_steps_match_the_oracle(T, orc, case):
     plan.close()
 
 
+# problems of K and K + 1 cells (six points) between larger ones
+SMALL = [6, 7, 6, 12, 7, 255, 256, 257]
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["periodic", "transmissive"])
+def test_smallest_problems_match_the_oracle(T, orc, bc):
+    """Six-point problems as short as the stencil: two steps compared with
+    the oracle problem by problem, and the persistent launch of the same two
+    steps in the same bits."""
+    U, dx, _ = ragged_batch(SMALL, seed0=41)
+    plan = T.BatchPlan(SMALL, dx, bc)
+    pers = T.BatchPlan(SMALL, dx, bc)
+    Ud = to_dev(U)
+    for step in range(2):
+        print(f"[batch small] bc={bc} step {step}", flush=True)
+        Uin = to_host(Ud)
+        plan.rk3(Ud, 6, T.LIM_MP, 1e-5, GAMMA, CFL, steps=1)
+        _, dt = plan.times()
+        Ug = to_host(Ud)
+        for p, n in enumerate(SMALL):
+            g = grid_of(n, dx[p], bc)
+            Up = problem(Uin, plan, p)
+            assert dt[p] == pytest.approx(CFL / orc.max_wave_speed(Up, g, GAMMA), rel=1e-13)
+            Uo = orc.rk3_step(Up, g, 6, 1, 1e-5, GAMMA, dt[p])
+            excl = rk3_excluded(orc, Up, g, 6, 1, 1e-5, dt[p])
+            assert excl.sum() < max(n // 2, 1), f"problem {p}: {excl.sum()} band cells"
+            assert_close_fields(problem(Ug, plan, p), Uo, exclude=excl, what=f"small bc={bc} step {step} problem {p}")
+    B = to_dev(U)
+    pers.rk3_persistent(B, 6, T.LIM_MP, 1e-5, GAMMA, CFL, steps=2)
+    assert np.array_equal(to_host(B), to_host(Ud)), "persistent launch differs from the eager steps"
+    plan.close()
+    pers.close()
+
+
 def test_every_tile_gives_the_same_bits(T):
     U, dx, _ = ragged_batch(SIZES, seed0=3)
     plan = T.BatchPlan(SIZES, dx, 1)
