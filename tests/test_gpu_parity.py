@@ -32,6 +32,8 @@ CASES = [
     ("euler3d_mp8_long_z", (80, 8, 16), 1, [0, 0, 0], 8, 1, 1e-7, None),
     ("min_size_6", (6,), 1, [0], 6, 1, 1e-5, None),
     ("min_size_8_trans", (8,), 1, [1], 8, 1, 1e-7, None),
+    ("min_size_3d_6", (6, 6, 6), 1, [0, 0, 0], 6, 1, 1e-5, None),
+    ("min_size_3d_8_mixed", (8, 8, 8), 1, [1, 0, 1], 8, 1, 1e-7, None),
     # limiter variants (Secs. 3.2.1, 4.2.5, 4.4) and classic renormalised TENO
     ("euler1d_va6", (300,), 1, [1], 6, 4, 1e-5, None),
     ("euler2d_va8", (21, 40), 1, [0, 1], 8, 4, 1e-6, None),
