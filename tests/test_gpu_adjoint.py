@@ -26,6 +26,10 @@ CASES = [
     ("scalar2d_va6", (15, 17), dict(ndim=2, n=[17, 15], dx=[0.05, 0.06], bc=[1, 0], system=0, adv=[0.6, -1.1]),
      6, 4, 1e-5),
     ("euler3d_mp6", (7, 8, 9), dict(ndim=3, n=[9, 8, 7], dx=[0.05, 0.06, 0.07], bc=[0, 1, 0], system=1), 6, 1, 1e-5),
+    # lines as short as the stencil
+    ("euler2d_min_mp6", (6, 6), dict(ndim=2, n=[6, 6], dx=[0.05, 0.06], bc=[0, 1], system=1), 6, 1, 1e-5),
+    ("euler1d_min_mp8_per", (8,), dict(ndim=1, n=[8], dx=[0.05], bc=[0], system=1), 8, 1, 1e-7),
+    ("scalar1d_min_tvd5_6_per", (6,), dict(ndim=1, n=[6], dx=[0.05], bc=[0], system=0, adv=[0.8]), 6, 3, 1e-5),
 ]
 IDS = [c[0] for c in CASES]
 
