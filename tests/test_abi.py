@@ -211,3 +211,12 @@ def test_batch_tile_shapes(lib):
         assert threads % 64 == 0 and fpt >= 1  # whole wavefronts
     with pytest.raises(T.TenomError):
         T.batch_tile_shape(T.BATCH_TILES)
+
+
+def test_missing_library_raises(monkeypatch):
+    """Without libtenom.so the binding raises instead of computing anything
+    another way (there is no fallback path)."""
+    monkeypatch.setattr(T, "_lib", None)
+    monkeypatch.setattr(T, "LIB_PATH", os.path.join(os.path.dirname(T.LIB_PATH), "no_such_libtenom.so"))
+    with pytest.raises(ImportError, match="missing"):
+        T.lib()
