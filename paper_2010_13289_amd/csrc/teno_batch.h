@@ -59,12 +59,14 @@ struct SegIn {
   int n, c_begin, bc;
 };
 
-// One segment, staged in LDS (at least RowStage<NF>::NE * (TPB * FPT + K - 1)
-// doubles).  Every thread of the workgroup calls it; the staging array is
-// free again when it returns.  `g` may live in LDS: its fields are read where
-// they are used, so that nothing of it is held through the face.
+// One segment, staged in LDS (`stage`: at least RowStage<NF>::NE *
+// (TPB * FPT + K - 1) doubles; `Fs`: the faces' fluxes, NF * (TPB * FPT + 1)
+// doubles).  Every thread of the workgroup calls it; both arrays may be
+// rewritten once every thread has returned.  `g` may live in LDS: its fields
+// are read where they are used, so that nothing of it is held through the
+// face.
 template <int NF, int K, int LIM, bool ADAPT, int TPB, int FPT>
-__device__ __forceinline__ void batch_segment(const SegIn& g, const FaceParams& fp, double* stage) {
+__device__ __forceinline__ void batch_segment(const SegIn& g, const FaceParams& fp, double* stage, double* Fs) {
   constexpr int SEG = BatchTile<TPB, FPT>::FACES;  // faces per workgroup
   constexpr int NC = SEG + K - 1;                  // staged cells
   const int t = threadIdx.x;
@@ -101,8 +103,6 @@ __device__ __forceinline__ void batch_segment(const SegIn& g, const FaceParams& 
   __syncthreads();
   __builtin_amdgcn_s_setprio(0);
 
-  double F[FPT][NF];
-  double us[FPT][NF];
   int nface, ncell;
   {
     const int n = g.n;
@@ -116,24 +116,13 @@ __device__ __forceinline__ void batch_segment(const SegIn& g, const FaceParams& 
     if (j < nface) {
       StagedCells<NF, K, 1, true> prov{stage, NC, j};
       uint32_t bits[2][NF];
-      face_flux<NF, K, LIM, ADAPT, false>(prov, fp, F[f], bits);
-    }
-    if (j < ncell) {
+      double F[NF];
+      face_flux<NF, K, LIM, ADAPT, false>(prov, fp, F, bits);
 #pragma unroll
-      for (int q = 0; q < NF; ++q) us[f][q] = stage[q * NC + j + K / 2];
-    }
-  }
-  __syncthreads();  // every face has read the staged cells
-  double* Fs = stage;  // reuse: [NF][SEG + 1]
-#pragma unroll
-  for (int f = 0; f < FPT; ++f) {
-    const int j = t + f * TPB;
-    if (j < nface) {
-#pragma unroll
-      for (int q = 0; q < NF; ++q) Fs[q * (SEG + 1) + j] = F[f][q];
+      for (int q = 0; q < NF; ++q) Fs[q * (SEG + 1) + j] = F[q];
     }
   }
-  __syncthreads();
+  __syncthreads();  // every face's flux is in Fs
   __builtin_amdgcn_s_setprio(3);
   {
     const int n = g.n;
@@ -152,7 +141,7 @@ __device__ __forceinline__ void batch_segment(const SegIn& g, const FaceParams& 
       for (int q = 0; q < NF; ++q) {
         const long o = q * total + cell;
         const double div = (Fs[q * (SEG + 1) + j] - Fs[q * (SEG + 1) + r]) * idx;
-        const double v = fma(dt, div, us[f][q]);
+        const double v = fma(dt, div, stage[q * NC + j + K / 2]);
         Uout[o] = (a != 0.0) ? fma(a, U0[o], b * v) : b * v;
       }
     }
@@ -164,6 +153,7 @@ template <int NF, int K, int LIM, bool ADAPT, int TPB, int FPT>
 __global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
   constexpr int NC = BatchTile<TPB, FPT>::FACES + K - 1;
   __shared__ double stage[RowStage<NF>::NE * NC];
+  __shared__ double Fs[NF * (BatchTile<TPB, FPT>::FACES + 1)];
   const int2 sg = p.segs[blockIdx.x];
   const int prob = sg.x;
   SegIn g;
@@ -179,7 +169,7 @@ __global__ __launch_bounds__(TPB) void k_batch_row(BatchParams<NF> p) {
   g.c_begin = sg.y;
   g.total = p.total;
   g.bc = p.bc;
-  batch_segment<NF, K, LIM, ADAPT, TPB, FPT>(g, p.fp, stage);
+  batch_segment<NF, K, LIM, ADAPT, TPB, FPT>(g, p.fp, stage, Fs);
 }
 
 // Signal rate (|u| + c)/dx of one 1D Euler cell (the CFL condition, Sec. 4).
@@ -272,6 +262,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   constexpr int SEG = BatchTile<TPB, FPT>::FACES;
   constexpr int NC = SEG + K - 1;
   __shared__ double stage[RowStage<NF>::NE * NC];
+  __shared__ double Fs[NF * (SEG + 1)];
   __shared__ unsigned long long rate;
   // The walk over (problem, step, stage, segment) is one loop; its four
   // counters are the only values carried from pass to pass (the arguments
@@ -344,7 +335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     long off = 0;
     asm volatile("" : "+s"(off));
     const PersistParams& pe = *(const PersistParams*)((const char*)&p + off);
-    batch_segment<NF, K, LIM, ADAPT, TPB, FPT>(g, pe.fp, stage);
+    batch_segment<NF, K, LIM, ADAPT, TPB, FPT>(g, pe.fp, stage, Fs);
     if (done && threadIdx.x == 0) take(pe);
     // the next pass rewrites g and the staging array, and when it begins a
     // new stage (or step, or problem) it reads what every thread of the
